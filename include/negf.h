@@ -1,0 +1,190 @@
+/*
+ * negf.h - C ABI of libnegf: real-space NEGF transmission on MI355X (gfx950).
+ *
+ * The library computes columns of the retarded Green's function
+ *     G(E) = A(E)^-1,   A(E) = E*1 - H + i(W_L + W_R)
+ * of a real-space operator H = -1/2 Lap_h + diag(V) + sum_p E_p b_p b_p^T on a
+ * uniform grid (Sec. II.C: finite-difference Laplacian, local potential and a
+ * non-local separable pseudopotential inside a cutoff), with z-only absorbing
+ * potentials W_L, W_R (Sec. II.B, Eqs. 4-5; they play the anti-Hermitian part
+ * of the lead self-energies, so the coupling matrices are Gamma = 2W).  Since
+ * H is real symmetric and W diagonal, A(E) is complex symmetric (Eq. 6).  The
+ * transmission is reduced from the block of G between the two absorbing
+ * regions (Eq. 7, with Gamma = 2W):
+ *     T(E) = 4 sum_{i in L, j in R} W_L,i W_R,j |G_ij(E)|^2 .
+ *
+ * Grid convention: point (ix,iy,iz) (0-based) sits at ((ix+1)h,(iy+1)h,(iz+1)h);
+ * linear index i = ix + nx*(iy + ny*iz) (x fastest); Dirichlet walls one
+ * spacing beyond the first and last points (ghost values are zero).  The
+ * Laplacian is the order-2R central star stencil along each axis, 1 <= R <= 6.
+ *
+ * Ownership: every input is copied before the call returns; the caller keeps
+ * ownership of all its buffers.  Outputs are caller-allocated.  Pointers are
+ * host pointers unless a parameter says "host or device", in which case the
+ * library asks the HIP runtime which kind it is.
+ *
+ * Errors: no exception crosses the ABI.  A status other than NEGF_OK leaves
+ * outputs undefined, except NEGF_E_NOT_CONVERGED, which returns every result
+ * together with per-item status codes.  negf_last_error() gives a message for
+ * the last failing call of the calling thread.
+ *
+ * Concurrency: a negf_op may be used by one thread at a time; distinct ops
+ * are independent.  Work is queued on opts->stream (a hipStream_t), or on a
+ * stream owned by the op when that is NULL; calls return after their work on
+ * that stream has finished.
+ */
+#ifndef NEGF_H
+#define NEGF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NEGF_OK = 0,
+    NEGF_E_INVALID_ARG = 1,    /* rejected before any device work */
+    NEGF_E_OUT_OF_MEMORY = 2,  /* device allocation failed; nothing leaked */
+    NEGF_E_DEVICE = 3,         /* a HIP call failed */
+    NEGF_E_NOT_CONVERGED = 4,  /* some item missed tol within max_iter */
+    NEGF_E_BREAKDOWN = 5       /* a COCG recurrence broke down (p^T A p or r^T r ~ 0) */
+} negf_status;
+
+/* per-item status codes written to item_status arrays */
+enum { NEGF_ITEM_CONVERGED = 0, NEGF_ITEM_MAX_ITER = 1, NEGF_ITEM_BREAKDOWN = 2 };
+
+/* negf_opts.precision */
+enum {
+    NEGF_FP64 = 0,  /* Krylov vectors, matvec, scalars and reductions in FP64 */
+    NEGF_MIXED = 1  /* FP32 matvec and Krylov vectors; FP64 scalars, dots,
+                       true residual b - A x, solution accumulation and T */
+};
+
+/* negf_opts.core */
+enum {
+    NEGF_CORE_AUTO = 0,
+    NEGF_CORE_PER_ENERGY = 1, /* one COCG run per (column, energy) item */
+    NEGF_CORE_MULTISHIFT = 2  /* one COCG run per column serves every energy */
+};
+
+/* negf_opts.direction for negf_transmission */
+enum {
+    NEGF_DIR_RL = 0, /* columns on the right CAP support, rows on the left */
+    NEGF_DIR_LR = 1  /* columns on the left, rows on the right (reciprocity) */
+};
+
+typedef struct { double re, im; } negf_c64;
+
+typedef struct {
+    int32_t nx, ny, nz; /* interior grid points per axis, each >= 1 */
+    double h;           /* grid spacing in bohr, > 0 */
+} negf_grid;
+
+/* Separable projectors b_p (CSR by projector): the values of b_p are
+ * val[offsets[p] .. offsets[p+1]) at grid indices idx[...]; E_p = e_kb[p]. */
+typedef struct {
+    int32_t n_proj;
+    const int64_t* offsets; /* n_proj + 1, offsets[0] = 0, non-decreasing */
+    const int32_t* idx;     /* offsets[n_proj] grid indices in [0, N) */
+    const double* val;      /* offsets[n_proj] real values */
+    const double* e_kb;     /* n_proj energies (Ha) */
+} negf_kb;
+
+typedef struct {
+    int32_t precision;   /* NEGF_FP64 or NEGF_MIXED */
+    int32_t core;        /* NEGF_CORE_* */
+    int32_t direction;   /* NEGF_DIR_* (negf_transmission only) */
+    double tol;          /* relative residual per (column, energy); FP64 path:
+                            COCG residual estimate; mixed path: true FP64
+                            residual ||b - A x|| / ||b||.  0 -> 1e-10 */
+    int32_t max_iter;    /* Krylov iterations per run; 0 -> 20000 */
+    int32_t block_width; /* columns (or items) per block; 0 -> auto */
+    int32_t shift_group; /* energies per multi-shift run; 0 -> all */
+    int32_t max_refine;  /* mixed: outer refinement steps; 0 -> 8 */
+    void* stream;        /* hipStream_t or NULL */
+} negf_opts;
+
+/* Optional diagnostics of negf_transmission.  Each array is nullable and is
+ * indexed [e * n_cols + c], n_cols = number of source columns
+ * (nx*ny*planes of the source CAP). */
+typedef struct {
+    int32_t* iters;          /* Krylov iterations used for the item */
+    double* resid;           /* final relative residual (see negf_opts.tol) */
+    double* t_col;           /* per-column transmission t_j(E) */
+    int32_t* item_status;    /* NEGF_ITEM_* */
+    int64_t total_iters;     /* out: sum of Krylov iterations over runs */
+    int32_t n_not_converged; /* out */
+    double seconds;          /* out: wall time of the device work */
+} negf_diag;
+
+typedef struct negf_op negf_op;
+
+/* Builds the operator of Sec. II.B-C on the current HIP device.
+ *   g           grid sizes and spacing
+ *   stencil_radius  R in 1..6 (order-2R finite differences)
+ *   v_local     N = nx*ny*nz local potential values (Ha), finite
+ *   kb          separable projectors, or NULL for none
+ *   cap_left_z  nz values W_L(z) >= 0, nonzero only on leading planes
+ *   cap_right_z nz values W_R(z) >= 0, nonzero only on trailing planes
+ * Requirements (else NEGF_E_INVALID_ARG): the two supports are disjoint,
+ * each is a contiguous run of at least R planes touching its wall (this
+ * makes A(E) nonsingular for real E without projectors), and no projector
+ * point lies on a CAP plane.  *out receives a new op; free with negf_destroy. */
+negf_status negf_build_operator(const negf_grid* g, int32_t stencil_radius,
+                                const double* v_local, const negf_kb* kb,
+                                const double* cap_left_z, const double* cap_right_z,
+                                negf_op** out);
+
+/* Y = A(E_c) X for a block of n_vec complex vectors (the matvec of the hot
+ * loop; Sec. II.C names it the bottleneck of iterative methods).
+ *   precision   NEGF_FP64 or NEGF_MIXED (FP32 arithmetic, FP64 in and out)
+ *   shifts      n_vec host energies E_c
+ *   x, y        [n_vec][N] host or device (both the same kind) */
+negf_status negf_apply_operator(negf_op* op, int32_t precision, int32_t n_vec,
+                                const double* shifts, const negf_c64* x, negf_c64* y);
+
+/* Columns of G(E) (Eq. 3): out[e][r][k] = (A(E_e)^-1 b_r)[row_idx[k]].
+ *   n_e, energies   host energies
+ *   n_rhs           number of right-hand sides
+ *   rhs_idx         n_rhs grid indices (b_r = unit vector), or NULL
+ *   rhs_dense       [n_rhs][N] host or device dense right-hand sides, or NULL
+ *                   (exactly one of rhs_idx / rhs_dense is non-NULL)
+ *   n_rows, row_idx rows to return; row_idx NULL means all N rows (n_rows = N)
+ *   out             [n_e][n_rhs][n_rows] host or device
+ *   item_status     [n_e][n_rhs] host, nullable */
+negf_status negf_solve_columns(negf_op* op, const negf_opts* opts, int32_t n_e,
+                               const double* energies, int32_t n_rhs,
+                               const int32_t* rhs_idx, const negf_c64* rhs_dense,
+                               int32_t n_rows, const int32_t* row_idx,
+                               negf_c64* out, int32_t* item_status);
+
+/* T(E) of Eq. 7 (factor 4 for Gamma = 2W) for n_e host energies into the
+ * host array T[n_e] (FP64).  diag is nullable. */
+negf_status negf_transmission(negf_op* op, const negf_opts* opts, int32_t n_e,
+                              const double* energies, double* T, negf_diag* diag);
+
+/* Adjoint gradient of L = sum_e weights[e] T(E_e) with respect to the local
+ * potential: dL_dV[r] = sum_e w_e 8 Re sum_{j in R} W_R,j lambda_j(r) g_j(r),
+ * with g_j = A^-1 e_j and lambda_j = A^-1 (W_L o conj(g_j)) solved with the
+ * same complex symmetric operator (A^T = A, Eq. 6).
+ *   weights   n_e host values; dL_dV  N host or device FP64;
+ *   T         optional host n_e output of T(E) (nullable). */
+negf_status negf_transmission_grad(negf_op* op, const negf_opts* opts, int32_t n_e,
+                                   const double* energies, const double* weights,
+                                   double* dL_dV, double* T);
+
+/* Frees the op and all device memory it owns.  NULL is a no-op. */
+void negf_destroy(negf_op* op);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* negf_last_error(void);
+
+/* Library version string. */
+const char* negf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NEGF_H */

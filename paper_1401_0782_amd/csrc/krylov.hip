@@ -1,0 +1,614 @@
+// Complex symmetric COCG recurrences on blocks of columns, for gfx950.
+//
+// A(E) is complex symmetric (Eq. 6), so the conjugate-orthogonal conjugate
+// gradient method uses the bilinear form u^T v (no conjugation) in place of
+// an inner product.  One iteration for the seed operator A0 = A(E_seed):
+//     p_k = r_k + beta_{k-1} p_{k-1};  q_k = A0 p_k;  alpha_k = rho_k / (p_k^T q_k)
+//     r_{k+1} = r_k - alpha_k q_k;     rho_{k+1} = r_{k+1}^T r_{k+1};  beta_k = rho_{k+1}/rho_k
+// Because the absorbing potential does not depend on E (the wide-band limit
+// of Sec. II.B), A(E) = A0 + (E - E_seed) 1 is a shifted family with the same
+// Krylov space, so one run per column serves every energy.
+//
+// All iteration state lives on the device (IterState) so that a chunk of
+// iterations can be replayed without host involvement; every kernel skips a
+// column whose done flag is set.
+//
+// Reductions are deterministic: each work-group writes one partial per column
+// (wave shuffles + LDS, FP64 accumulation) and a per-column reduction kernel
+// sums the partials in a fixed order.
+#include "negf_internal.h"
+
+namespace {
+
+constexpr int kT = 256;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// block-wide sum of NV doubles held by every thread (result valid in thread 0)
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double* lds) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) lds[wave * NV + j] = v[j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kT / 64; ++w) {
+#pragma unroll
+            for (int j = 0; j < NV; ++j) v[j] += lds[w * NV + j];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename R>
+__device__ inline double2 to_d2(cplx_t<R> a) { return make_double2((double)a.x, (double)a.y); }
+
+// ---------------------------------------------------------------------------
+// p = r + beta p  (p = r on the first iteration)
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kT) void k_p_update(const cplx_t<R>* __restrict__ r,
+                                                 cplx_t<R>* __restrict__ p, int64_t N,
+                                                 const int* __restrict__ done,
+                                                 const int* __restrict__ kit,
+                                                 const double2* __restrict__ beta) {
+    const int c = blockIdx.y;
+    if (done[c]) return;
+    const bool first = kit[c] == 0;
+    const double2 b = beta[c];
+    const cplx_t<R>* rc = r + (int64_t)c * N;
+    cplx_t<R>* pc = p + (int64_t)c * N;
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kT) {
+        const cplx_t<R> rv = rc[i];
+        cplx_t<R> o;
+        if (first) {
+            o = rv;
+        } else {
+            const cplx_t<R> pv = pc[i];
+            o.x = rv.x + (R)b.x * pv.x - (R)b.y * pv.y;
+            o.y = rv.y + (R)b.x * pv.y + (R)b.y * pv.x;
+        }
+        pc[i] = o;
+    }
+}
+
+// partial sums of the bilinear p^T q per (work-group, column)
+template <typename R>
+__global__ __launch_bounds__(kT) void k_dot(const cplx_t<R>* __restrict__ a,
+                                            const cplx_t<R>* __restrict__ b, int64_t N,
+                                            const int* __restrict__ done,
+                                            double2* __restrict__ part) {
+    __shared__ double lds[2 * kT / 64];
+    const int c = blockIdx.y;
+    if (done[c]) return;
+    const cplx_t<R>* ac = a + (int64_t)c * N;
+    const cplx_t<R>* bc = b + (int64_t)c * N;
+    double s[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kT) {
+        const cplx_t<R> u = ac[i], v = bc[i];
+        s[0] += (double)u.x * v.x - (double)u.y * v.y;
+        s[1] += (double)u.x * v.y + (double)u.y * v.x;
+    }
+    block_sum<2>(s, lds);
+    if (threadIdx.x == 0) part[(int64_t)c * gridDim.x + blockIdx.x] = make_double2(s[0], s[1]);
+}
+
+// alpha = rho / (p^T q) per column
+__global__ __launch_bounds__(kT) void k_reduce_alpha(const double2* __restrict__ part, int nblk,
+                                                     IterState st) {
+    __shared__ double lds[2 * kT / 64];
+    const int c = blockIdx.x;
+    if (st.done[c]) return;
+    double s[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += kT) {
+        const double2 v = part[(int64_t)c * nblk + b];
+        s[0] += v.x;
+        s[1] += v.y;
+    }
+    block_sum<2>(s, lds);
+    if (threadIdx.x == 0) {
+        const double2 mu = make_double2(s[0], s[1]);
+        const double2 a = cdiv(st.rho[c], mu);
+        if (!cfinite(a) || (mu.x == 0.0 && mu.y == 0.0)) {
+            st.done[c] = 1 + NEGF_ITEM_BREAKDOWN;
+            return;
+        }
+        st.alpha[c] = a;
+        if (st.a_hist) st.a_hist[(int64_t)c * st.max_iter + st.k[c]] = a;
+    }
+}
+
+// r -= alpha q (and x += alpha p when x != null); partials of r^T r and r^H r
+template <typename R>
+__global__ __launch_bounds__(kT) void k_r_update(cplx_t<R>* __restrict__ r,
+                                                 const cplx_t<R>* __restrict__ q,
+                                                 const cplx_t<R>* __restrict__ p,
+                                                 cplx_t<R>* __restrict__ x, int64_t N,
+                                                 const int* __restrict__ done,
+                                                 const double2* __restrict__ alpha,
+                                                 double2* __restrict__ part_rr,
+                                                 double* __restrict__ part_nn) {
+    __shared__ double lds[3 * kT / 64];
+    const int c = blockIdx.y;
+    if (done[c]) return;
+    const double2 a = alpha[c];
+    const R ax = (R)a.x, ay = (R)a.y;
+    cplx_t<R>* rc = r + (int64_t)c * N;
+    const cplx_t<R>* qc = q + (int64_t)c * N;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kT) {
+        const cplx_t<R> qv = qc[i];
+        cplx_t<R> rv = rc[i];
+        rv.x -= ax * qv.x - ay * qv.y;
+        rv.y -= ax * qv.y + ay * qv.x;
+        rc[i] = rv;
+        if (x) {
+            const cplx_t<R> pv = p[(int64_t)c * N + i];
+            cplx_t<R> xv = x[(int64_t)c * N + i];
+            xv.x += ax * pv.x - ay * pv.y;
+            xv.y += ax * pv.y + ay * pv.x;
+            x[(int64_t)c * N + i] = xv;
+        }
+        const double rx = rv.x, ry = rv.y;
+        s[0] += rx * rx - ry * ry;
+        s[1] += 2.0 * rx * ry;
+        s[2] += rx * rx + ry * ry;
+    }
+    block_sum<3>(s, lds);
+    if (threadIdx.x == 0) {
+        part_rr[(int64_t)c * gridDim.x + blockIdx.x] = make_double2(s[0], s[1]);
+        part_nn[(int64_t)c * gridDim.x + blockIdx.x] = s[2];
+    }
+}
+
+// Multi-shift bookkeeping for one column per work-group.
+//   rho_{k+1}, s_{k+1} = ||r_{k+1}||, beta_k; then for every shift delta the
+//   scaled residual polynomial value pih = pi * s_0 / s_k, with
+//   pi_{k+1} = (1 + alpha_k delta) pi_k + (alpha_k beta_{k-1}/alpha_{k-1}) (pi_k - pi_{k-1}),
+//   so that ||r^delta_k|| / ||b|| = 1 / |pih_k|.
+__global__ __launch_bounds__(kT) void k_reduce_beta_ms(const double2* __restrict__ part_rr,
+                                                       const double* __restrict__ part_nn,
+                                                       int nblk, IterState st) {
+    __shared__ double lds[3 * kT / 64];
+    __shared__ double2 sh_sc[4];
+    __shared__ int sh_all;
+    const int c = blockIdx.x;
+    if (st.done[c]) return;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += kT) {
+        const double2 v = part_rr[(int64_t)c * nblk + b];
+        s[0] += v.x;
+        s[1] += v.y;
+        s[2] += part_nn[(int64_t)c * nblk + b];
+    }
+    block_sum<3>(s, lds);
+    const int k = st.k[c];
+    if (threadIdx.x == 0) {
+        const double2 rho_new = make_double2(s[0], s[1]);
+        const double snew = sqrt(s[2]);
+        const double2 a = st.alpha[c];
+        const double2 bprev = st.beta[c];
+        const double2 aprev = (k > 0) ? st.a_hist[(int64_t)c * st.max_iter + k - 1] : make_double2(1.0, 0.0);
+        const double2 beta = cdiv(rho_new, st.rho[c]);
+        const double* sh = st.s_hist + (int64_t)c * (st.max_iter + 1);
+        st.s_hist[(int64_t)c * (st.max_iter + 1) + k + 1] = snew;
+        st.b_hist[(int64_t)c * st.max_iter + k] = beta;
+        // scalars for the shift update
+        const double2 ck = (k > 0) ? cdiv(cmul(a, bprev), aprev) : make_double2(0.0, 0.0);
+        const double sk = sh[k];
+        const double skm1 = (k > 0) ? sh[k - 1] : sh[0];
+        sh_sc[0] = a;
+        sh_sc[1] = ck;
+        sh_sc[2] = make_double2(sk / snew, skm1 / snew);
+        sh_sc[3] = make_double2(snew, cfinite(beta) ? 1.0 : 0.0);
+        st.rho[c] = rho_new;
+        st.beta[c] = beta;
+        st.rnorm[c] = snew;
+        sh_all = 1;
+    }
+    __syncthreads();
+    const double2 a = sh_sc[0], ck = sh_sc[1];
+    const double r1 = sh_sc[2].x, r2 = sh_sc[2].y;
+    int all = 1;
+    for (int g = threadIdx.x; g < st.ng; g += kT) {
+        const int64_t o = (int64_t)c * st.ng + g;
+        // A shift whose residual met tol keeps its flag: shifts far from the
+        // seed keep converging geometrically and their pih would overflow.
+        // The final coefficients come from the tridiagonal solve, not from pih.
+        if (st.sconv[o]) continue;
+        const double d = st.deltas[o];
+        const double2 pk = st.pih[o], pkm1 = st.pih_prev[o];
+        // (1 + a d) pk + ck pk, scaled by s_k/s_{k+1}; minus ck pkm1 s_{k-1}/s_{k+1}
+        const double2 t1 = cadd(cmul(mk(1.0 + a.x * d, a.y * d), pk), cmul(ck, pk));
+        const double2 t2 = cmul(ck, pkm1);
+        const double2 pn = mk(r1 * t1.x - r2 * t2.x, r1 * t1.y - r2 * t2.y);
+        st.pih_prev[o] = pk;
+        st.pih[o] = pn;
+        const double res = 1.0 / sqrt(cabs2(pn));
+        if (res <= st.tol) st.sconv[o] = 1;
+        else all = 0;
+    }
+    if (!all) atomicAnd(&sh_all, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st.k[c] = k + 1;
+        if (sh_sc[3].y == 0.0) {
+            // rho_{k+1} / rho_k not finite: r^T r vanished
+            st.done[c] = (sh_sc[3].x == 0.0) ? 1 + NEGF_ITEM_CONVERGED : 1 + NEGF_ITEM_BREAKDOWN;
+        } else if (sh_all) {
+            st.done[c] = 1 + NEGF_ITEM_CONVERGED;
+        } else if (k + 1 >= st.max_iter) {
+            st.done[c] = 1 + NEGF_ITEM_MAX_ITER;
+        }
+    }
+}
+
+// Single-system bookkeeping (per-energy core): converged when ||r|| <= tol ||b||.
+__global__ __launch_bounds__(kT) void k_reduce_beta_single(const double2* __restrict__ part_rr,
+                                                           const double* __restrict__ part_nn,
+                                                           int nblk, IterState st,
+                                                           double inner_tol) {
+    __shared__ double lds[3 * kT / 64];
+    const int c = blockIdx.x;
+    if (st.done[c]) return;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += kT) {
+        const double2 v = part_rr[(int64_t)c * nblk + b];
+        s[0] += v.x;
+        s[1] += v.y;
+        s[2] += part_nn[(int64_t)c * nblk + b];
+    }
+    block_sum<3>(s, lds);
+    if (threadIdx.x == 0) {
+        const int k = st.k[c];
+        const double2 rho_new = make_double2(s[0], s[1]);
+        const double snew = sqrt(s[2]);
+        const double2 beta = cdiv(rho_new, st.rho[c]);
+        st.rho[c] = rho_new;
+        st.beta[c] = beta;
+        st.rnorm[c] = snew;
+        st.k[c] = k + 1;
+        if (snew <= inner_tol * st.bnorm[c]) {
+            st.done[c] = 1 + NEGF_ITEM_CONVERGED;
+        } else if (!cfinite(beta)) {
+            st.done[c] = 1 + NEGF_ITEM_BREAKDOWN;
+        } else if (k + 1 >= st.max_iter) {
+            st.done[c] = 1 + NEGF_ITEM_MAX_ITER;
+        }
+    }
+}
+
+// copy r[c][rows] into the stored-vector slot k[c] + slot_offset
+template <typename R>
+__global__ __launch_bounds__(kT) void k_store_rows(const cplx_t<R>* __restrict__ r, int64_t N,
+                                                   const int* __restrict__ rows, int64_t row0,
+                                                   int n_rows, double2* const* __restrict__ tab,
+                                                   int chunk_iters, int w,
+                                                   const int* __restrict__ done,
+                                                   const int* __restrict__ kit, int slot_offset) {
+    const int c = blockIdx.y;
+    if (done[c]) return;
+    const int slot = kit[c] + slot_offset;
+    double2* dst = tab[slot / chunk_iters] + ((int64_t)(slot % chunk_iters) * w + c) * n_rows;
+    const cplx_t<R>* rc = r + (int64_t)c * N;
+    for (int i = blockIdx.x * kT + threadIdx.x; i < n_rows; i += gridDim.x * kT) {
+        const int64_t gi = rows ? (int64_t)rows[i] : row0 + i;
+        dst[i] = to_d2<R>(rc[gi]);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+int part_blocks(int64_t n) {
+    int64_t b = (n + 4 * kT - 1) / (4 * kT);
+    if (b < 1) b = 1;
+    if (b > 512) b = 512;
+    return (int)b;
+}
+
+template <typename R>
+void launch_p_update(const cplx_t<R>* r, cplx_t<R>* p, const IterState& st, int64_t N,
+                     hipStream_t s) {
+    dim3 g(part_blocks(N), st.w);
+    hipLaunchKernelGGL((k_p_update<R>), g, dim3(kT), 0, s, r, p, N, st.done, st.k, st.beta);
+}
+
+template <typename R>
+void launch_dot_pq(const cplx_t<R>* p, const cplx_t<R>* q, double2* part, const IterState& st,
+                   int64_t N, hipStream_t s) {
+    dim3 g(part_blocks(N), st.w);
+    hipLaunchKernelGGL((k_dot<R>), g, dim3(kT), 0, s, p, q, N, st.done, part);
+}
+
+void launch_reduce_alpha(const double2* part, int nblk, IterState st, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_alpha, dim3(st.w), dim3(kT), 0, s, part, nblk, st);
+}
+
+template <typename R>
+void launch_r_update(cplx_t<R>* r, const cplx_t<R>* q, cplx_t<R>* p, cplx_t<R>* x,
+                     double2* part_rr, double* part_nn, const IterState& st, int64_t N,
+                     hipStream_t s) {
+    dim3 g(part_blocks(N), st.w);
+    hipLaunchKernelGGL((k_r_update<R>), g, dim3(kT), 0, s, r, q, p, x, N, st.done, st.alpha,
+                       part_rr, part_nn);
+}
+
+void launch_reduce_beta_multishift(const double2* part_rr, const double* part_nn, int nblk,
+                                   IterState st, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_beta_ms, dim3(st.w), dim3(kT), 0, s, part_rr, part_nn, nblk, st);
+}
+
+void launch_reduce_beta_single(const double2* part_rr, const double* part_nn, int nblk,
+                               IterState st, double inner_tol, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_beta_single, dim3(st.w), dim3(kT), 0, s, part_rr, part_nn, nblk,
+                       st, inner_tol);
+}
+
+template <typename R>
+void launch_store_rows(const cplx_t<R>* r, int64_t N, int w, const int* rows, int64_t row0,
+                       int n_rows, double2* const* chunk_tab, int chunk_iters,
+                       const IterState& st, int slot_offset, hipStream_t s) {
+    int gx = (n_rows + kT - 1) / kT;
+    if (gx > 256) gx = 256;
+    dim3 g(gx, w);
+    hipLaunchKernelGGL((k_store_rows<R>), g, dim3(kT), 0, s, r, N, rows, row0, n_rows, chunk_tab,
+                       chunk_iters, w, st.done, st.k, slot_offset);
+}
+
+#define INST(R)                                                                                  \
+    template void launch_p_update<R>(const cplx_t<R>*, cplx_t<R>*, const IterState&, int64_t,  \
+                                     hipStream_t);                                              \
+    template void launch_dot_pq<R>(const cplx_t<R>*, const cplx_t<R>*, double2*,               \
+                                   const IterState&, int64_t, hipStream_t);                     \
+    template void launch_r_update<R>(cplx_t<R>*, const cplx_t<R>*, cplx_t<R>*, cplx_t<R>*,      \
+                                     double2*, double*, const IterState&, int64_t, hipStream_t); \
+    template void launch_store_rows<R>(const cplx_t<R>*, int64_t, int, const int*, int64_t, int, \
+                                       double2* const*, int, const IterState&, int, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+// ---------------------------------------------------------------------------
+// initialisation and the per-energy (refined) solver helpers
+// ---------------------------------------------------------------------------
+namespace {
+
+// r[c] = e_{cols[c]} (unit right-hand sides); also b64 when given
+template <typename R>
+__global__ __launch_bounds__(kT) void k_init_unit(cplx_t<R>* __restrict__ r, double2* __restrict__ b64,
+                                                  int64_t N, const int* __restrict__ cols) {
+    const int c = blockIdx.y;
+    const int j = cols[c];
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kT) {
+        cplx_t<R> v; v.x = (i == j) ? (R)1 : (R)0; v.y = 0;
+        r[(int64_t)c * N + i] = v;
+        if (b64) b64[(int64_t)c * N + i] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    }
+}
+
+// partials of v^T v and v^H v (for initial scalars)
+template <typename R>
+__global__ __launch_bounds__(kT) void k_norms(const cplx_t<R>* __restrict__ v, int64_t N,
+                                              const int* __restrict__ skip,
+                                              double2* __restrict__ part_rr,
+                                              double* __restrict__ part_nn) {
+    __shared__ double lds[3 * kT / 64];
+    const int c = blockIdx.y;
+    if (skip && skip[c]) return;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kT) {
+        const cplx_t<R> u = v[(int64_t)c * N + i];
+        const double x = u.x, y = u.y;
+        s[0] += x * x - y * y;
+        s[1] += 2.0 * x * y;
+        s[2] += x * x + y * y;
+    }
+    block_sum<3>(s, lds);
+    if (threadIdx.x == 0) {
+        part_rr[(int64_t)c * gridDim.x + blockIdx.x] = make_double2(s[0], s[1]);
+        part_nn[(int64_t)c * gridDim.x + blockIdx.x] = s[2];
+    }
+}
+
+// start a COCG run: rho = r^T r, bnorm = s_0 = ||r||, k = 0, beta = 0, pih = 1.
+// Columns flagged in skip start (and stay) done.
+__global__ __launch_bounds__(kT) void k_reduce_init(const double2* __restrict__ part_rr,
+                                                    const double* __restrict__ part_nn, int nblk,
+                                                    IterState st, const int* __restrict__ skip) {
+    __shared__ double lds[3 * kT / 64];
+    const int c = blockIdx.x;
+    double s[3] = {0.0, 0.0, 0.0};
+    const bool sk = skip && skip[c];
+    if (!sk) {
+        for (int b = threadIdx.x; b < nblk; b += kT) {
+            const double2 v = part_rr[(int64_t)c * nblk + b];
+            s[0] += v.x;
+            s[1] += v.y;
+            s[2] += part_nn[(int64_t)c * nblk + b];
+        }
+    }
+    block_sum<3>(s, lds);
+    if (threadIdx.x == 0) {
+        const double n = sqrt(s[2]);
+        st.rho[c] = make_double2(s[0], s[1]);
+        st.bnorm[c] = n;
+        st.rnorm[c] = n;
+        st.beta[c] = make_double2(0.0, 0.0);
+        st.alpha[c] = make_double2(0.0, 0.0);
+        st.k[c] = 0;
+        st.done[c] = sk ? 1 + NEGF_ITEM_CONVERGED : ((n == 0.0) ? 1 + NEGF_ITEM_CONVERGED : 0);
+        if (st.s_hist) st.s_hist[(int64_t)c * (st.max_iter + 1)] = n;
+    }
+    if (st.pih) {
+        for (int g = threadIdx.x; g < st.ng; g += kT) {
+            st.pih[(int64_t)c * st.ng + g] = make_double2(1.0, 0.0);
+            st.pih_prev[(int64_t)c * st.ng + g] = make_double2(1.0, 0.0);
+            st.sconv[(int64_t)c * st.ng + g] = 0;
+        }
+    }
+}
+
+// r64 = b - q64; partial ||r64||^2 (skip: outer-converged items)
+__global__ __launch_bounds__(kT) void k_residual(const double2* __restrict__ b,
+                                                 const double2* __restrict__ q,
+                                                 double2* __restrict__ r, int64_t N,
+                                                 const int* __restrict__ skip,
+                                                 double* __restrict__ part) {
+    __shared__ double lds[kT / 64];
+    const int c = blockIdx.y;
+    if (skip[c]) return;
+    double s[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kT) {
+        const int64_t o = (int64_t)c * N + i;
+        const double2 v = csub(b[o], q[o]);
+        r[o] = v;
+        s[0] += cabs2(v);
+    }
+    block_sum<1>(s, lds);
+    if (threadIdx.x == 0) part[(int64_t)c * gridDim.x + blockIdx.x] = s[0];
+}
+
+// nu[c] = sqrt(sum part); outer done when nu <= tol * bnorm64
+__global__ __launch_bounds__(kT) void k_reduce_residual(const double* __restrict__ part, int nblk,
+                                                        int* __restrict__ odone,
+                                                        const double* __restrict__ bnorm64,
+                                                        double* __restrict__ nu, double tol,
+                                                        double* __restrict__ resid_out) {
+    __shared__ double lds[kT / 64];
+    const int c = blockIdx.x;
+    if (odone[c]) return;
+    double s[1] = {0.0};
+    for (int b = threadIdx.x; b < nblk; b += kT) s[0] += part[(int64_t)c * nblk + b];
+    block_sum<1>(s, lds);
+    if (threadIdx.x == 0) {
+        const double n = sqrt(s[0]);
+        nu[c] = n;
+        // without a reference norm (the first residual is b itself) only a
+        // zero right-hand side counts as converged
+        const double rel = bnorm64 ? ((bnorm64[c] > 0) ? n / bnorm64[c] : 0.0) : (n > 0 ? 1.0 : 0.0);
+        resid_out[c] = rel;
+        if (rel <= tol) odone[c] = 1;
+    }
+}
+
+// inner right-hand side: rin = r64 / nu (converted), d = 0
+template <typename R>
+__global__ __launch_bounds__(kT) void k_scale_convert(const double2* __restrict__ r64,
+                                                      cplx_t<R>* __restrict__ rin,
+                                                      cplx_t<R>* __restrict__ d, int64_t N,
+                                                      const int* __restrict__ skip,
+                                                      const double* __restrict__ nu) {
+    const int c = blockIdx.y;
+    if (skip[c]) return;
+    const double inv = 1.0 / nu[c];
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kT) {
+        const int64_t o = (int64_t)c * N + i;
+        const double2 v = r64[o];
+        cplx_t<R> t; t.x = (R)(v.x * inv); t.y = (R)(v.y * inv);
+        rin[o] = t;
+        cplx_t<R> z; z.x = 0; z.y = 0;
+        d[o] = z;
+    }
+}
+
+// x64 += nu * d
+template <typename R>
+__global__ __launch_bounds__(kT) void k_accumulate(double2* __restrict__ x64,
+                                                   const cplx_t<R>* __restrict__ d, int64_t N,
+                                                   const int* __restrict__ skip,
+                                                   const double* __restrict__ nu) {
+    const int c = blockIdx.y;
+    if (skip[c]) return;
+    const double s = nu[c];
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kT) {
+        const int64_t o = (int64_t)c * N + i;
+        const cplx_t<R> v = d[o];
+        double2 xv = x64[o];
+        xv.x += s * (double)v.x;
+        xv.y += s * (double)v.y;
+        x64[o] = xv;
+    }
+}
+
+// t[c] = col_w[c] * sum_{i < n_rows} row_w[i] |x64[c][row0 + i]|^2 (one work-group per column)
+__global__ __launch_bounds__(kT) void k_weighted_norm(const double2* __restrict__ x64, int64_t N,
+                                                      int64_t row0, int n_rows,
+                                                      const double* __restrict__ row_w,
+                                                      const double* __restrict__ col_w,
+                                                      double* __restrict__ t) {
+    __shared__ double lds[kT / 64];
+    const int c = blockIdx.x;
+    double s[1] = {0.0};
+    for (int i = threadIdx.x; i < n_rows; i += kT) s[0] += row_w[i] * cabs2(x64[(int64_t)c * N + row0 + i]);
+    block_sum<1>(s, lds);
+    if (threadIdx.x == 0) t[c] = col_w[c] * s[0];
+}
+
+}  // namespace
+
+template <typename R>
+void launch_init_unit(cplx_t<R>* r, double2* b64, int64_t N, int w, const int* cols, hipStream_t s) {
+    dim3 g(part_blocks(N), w);
+    hipLaunchKernelGGL((k_init_unit<R>), g, dim3(kT), 0, s, r, b64, N, cols);
+}
+template <typename R>
+void launch_norms(const cplx_t<R>* v, int64_t N, int w, const int* skip, double2* part_rr,
+                  double* part_nn, hipStream_t s) {
+    dim3 g(part_blocks(N), w);
+    hipLaunchKernelGGL((k_norms<R>), g, dim3(kT), 0, s, v, N, skip, part_rr, part_nn);
+}
+void launch_reduce_init(const double2* part_rr, const double* part_nn, int nblk, IterState st,
+                        const int* skip, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_init, dim3(st.w), dim3(kT), 0, s, part_rr, part_nn, nblk, st, skip);
+}
+void launch_residual(const double2* b, const double2* q, double2* r, int64_t N, int w,
+                     const int* skip, double* part, hipStream_t s) {
+    dim3 g(part_blocks(N), w);
+    hipLaunchKernelGGL(k_residual, g, dim3(kT), 0, s, b, q, r, N, skip, part);
+}
+void launch_reduce_residual(const double* part, int nblk, int w, int* odone, const double* bnorm64,
+                            double* nu, double tol, double* resid_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_residual, dim3(w), dim3(kT), 0, s, part, nblk, odone, bnorm64, nu,
+                       tol, resid_out);
+}
+template <typename R>
+void launch_scale_convert(const double2* r64, cplx_t<R>* rin, cplx_t<R>* d, int64_t N, int w,
+                          const int* skip, const double* nu, hipStream_t s) {
+    dim3 g(part_blocks(N), w);
+    hipLaunchKernelGGL((k_scale_convert<R>), g, dim3(kT), 0, s, r64, rin, d, N, skip, nu);
+}
+template <typename R>
+void launch_accumulate(double2* x64, const cplx_t<R>* d, int64_t N, int w, const int* skip,
+                       const double* nu, hipStream_t s) {
+    dim3 g(part_blocks(N), w);
+    hipLaunchKernelGGL((k_accumulate<R>), g, dim3(kT), 0, s, x64, d, N, skip, nu);
+}
+void launch_weighted_norm(const double2* x64, int64_t N, int w, int64_t row0, int n_rows,
+                          const double* row_w, const double* col_w, double* t, hipStream_t s) {
+    hipLaunchKernelGGL(k_weighted_norm, dim3(w), dim3(kT), 0, s, x64, N, row0, n_rows, row_w,
+                       col_w, t);
+}
+
+#define INST2(R)                                                                                 \
+    template void launch_init_unit<R>(cplx_t<R>*, double2*, int64_t, int, const int*,           \
+                                      hipStream_t);                                             \
+    template void launch_norms<R>(const cplx_t<R>*, int64_t, int, const int*, double2*,        \
+                                  double*, hipStream_t);                                        \
+    template void launch_scale_convert<R>(const double2*, cplx_t<R>*, cplx_t<R>*, int64_t, int, \
+                                          const int*, const double*, hipStream_t);              \
+    template void launch_accumulate<R>(double2*, const cplx_t<R>*, int64_t, int, const int*,    \
+                                       const double*, hipStream_t);
+INST2(double)
+INST2(float)
+#undef INST2

@@ -1,0 +1,1206 @@
+// C ABI of libnegf: operator construction, the two solver cores and the
+// transmission reduction.  Host orchestration only; every step of the hot
+// path runs in the kernels of stencil.hip, krylov.hip and shift.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <chrono>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "negf_internal.h"
+
+// launchers defined in krylov.hip (kept out of the shared header because only
+// this file calls them)
+template <typename R>
+void launch_init_unit(cplx_t<R>* r, double2* b64, int64_t N, int w, const int* cols, hipStream_t s);
+template <typename R>
+void launch_norms(const cplx_t<R>* v, int64_t N, int w, const int* skip, double2* part_rr,
+                  double* part_nn, hipStream_t s);
+void launch_reduce_init(const double2* part_rr, const double* part_nn, int nblk, IterState st,
+                        const int* skip, hipStream_t s);
+void launch_residual(const double2* b, const double2* q, double2* r, int64_t N, int w,
+                     const int* skip, double* part, hipStream_t s);
+void launch_reduce_residual(const double* part, int nblk, int w, int* odone, const double* bnorm64,
+                            double* nu, double tol, double* resid_out, hipStream_t s);
+template <typename R>
+void launch_scale_convert(const double2* r64, cplx_t<R>* rin, cplx_t<R>* d, int64_t N, int w,
+                          const int* skip, const double* nu, hipStream_t s);
+template <typename R>
+void launch_accumulate(double2* x64, const cplx_t<R>* d, int64_t N, int w, const int* skip,
+                       const double* nu, hipStream_t s);
+void launch_weighted_norm(const double2* x64, int64_t N, int w, int64_t row0, int n_rows,
+                          const double* row_w, const double* col_w, double* t, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+negf_status hip_fail(hipError_t e, const char* what, int line) {
+    set_error("HIP error %d (%s) in %s at line %d", (int)e, hipGetErrorString(e), what, line);
+    return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? NEGF_E_OUT_OF_MEMORY
+                                                                        : NEGF_E_DEVICE;
+}
+
+#define CHK(x)                                  \
+    do {                                        \
+        negf_status _s = (x);                   \
+        if (_s != NEGF_OK) return _s;           \
+    } while (0)
+
+// Test hook: NEGF_TEST_FAIL_ALLOC=k makes the k-th workspace allocation of the
+// process fail (exercises the out-of-memory path without exhausting HBM).
+static long g_alloc_count = 0;
+
+static negf_status dev_alloc(void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    ++g_alloc_count;
+    if (const char* env = getenv("NEGF_TEST_FAIL_ALLOC")) {
+        if (atol(env) == g_alloc_count) {
+            set_error("allocation of %zu bytes failed (test hook)", bytes);
+            return NEGF_E_OUT_OF_MEMORY;
+        }
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        set_error("device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+        return NEGF_E_OUT_OF_MEMORY;
+    }
+    return NEGF_OK;
+}
+
+negf_status ws_get(negf_op* op, int slot, size_t bytes, void** out) {
+    Buffer& b = op->bufs[slot];
+    if (b.bytes < bytes) {
+        if (b.ptr) (void)hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+        CHK(dev_alloc(&b.ptr, bytes));
+        b.bytes = bytes;
+    }
+    *out = b.ptr;
+    return NEGF_OK;
+}
+
+template <typename T>
+static negf_status ws(negf_op* op, int slot, size_t count, T** out) {
+    void* p = nullptr;
+    CHK(ws_get(op, slot, count * sizeof(T), &p));
+    *out = static_cast<T*>(p);
+    return NEGF_OK;
+}
+
+static bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice;
+}
+
+static hipStream_t pick_stream(negf_op* op, const negf_opts* o) {
+    return (o && o->stream) ? (hipStream_t)o->stream : op->own_stream;
+}
+
+// ---------------------------------------------------------------------------
+// operator construction
+// ---------------------------------------------------------------------------
+static void fd_weights(int R, double* c) {
+    // order-2R central second derivative: c_m = 2(-1)^(m+1) (R!)^2 / (m^2 (R-m)! (R+m)!),
+    // c_0 = -2 sum_m c_m
+    double fact[16];
+    fact[0] = 1.0;
+    for (int i = 1; i < 16; ++i) fact[i] = fact[i - 1] * i;
+    double s = 0.0;
+    for (int m = 1; m <= R; ++m) {
+        c[m] = 2.0 * ((m % 2) ? 1.0 : -1.0) * fact[R] * fact[R] / ((double)m * m * fact[R - m] * fact[R + m]);
+        s += c[m];
+    }
+    c[0] = -2.0 * s;
+}
+
+static negf_status plane_run(const double* cap, int nz, bool leading, int* z0, int* z1) {
+    // supported planes must be one contiguous run touching the wall
+    int first = -1, last = -1;
+    for (int z = 0; z < nz; ++z) {
+        if (!(cap[z] >= 0.0) || !std::isfinite(cap[z])) {
+            set_error("CAP value at plane %d is negative or not finite", z);
+            return NEGF_E_INVALID_ARG;
+        }
+        if (cap[z] > 0.0) {
+            if (first < 0) first = z;
+            last = z;
+        }
+    }
+    if (first < 0) {
+        set_error("a CAP profile is identically zero");
+        return NEGF_E_INVALID_ARG;
+    }
+    for (int z = first; z <= last; ++z)
+        if (!(cap[z] > 0.0)) {
+            set_error("CAP support is not a contiguous run of planes");
+            return NEGF_E_INVALID_ARG;
+        }
+    if (leading && first != 0) {
+        set_error("left CAP must start at plane 0");
+        return NEGF_E_INVALID_ARG;
+    }
+    if (!leading && last != nz - 1) {
+        set_error("right CAP must end at plane nz-1");
+        return NEGF_E_INVALID_ARG;
+    }
+    *z0 = first;
+    *z1 = last + 1;
+    return NEGF_OK;
+}
+
+static void free_op(negf_op* op) {
+    if (!op) return;
+    if (op->device < 0) {  // never reached the device
+        delete op;
+        return;
+    }
+    (void)hipSetDevice(op->device);
+    void* ptrs[] = {op->d_v, op->d_wz, op->d_wl, op->d_wr, op->kb.off, op->kb.idx, op->kb.val,
+                    op->kb.valf, op->kb.e, op->kb.pts, op->kb.pt_off, op->kb.pt_proj, op->kb.pt_val};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    for (auto& b : op->bufs)
+        if (b.ptr) (void)hipFree(b.ptr);
+    for (auto& b : op->vchunks)
+        if (b.ptr) (void)hipFree(b.ptr);
+    if (op->own_stream) (void)hipStreamDestroy(op->own_stream);
+    delete op;
+}
+
+template <typename T>
+static negf_status upload(T** dst, const T* src, size_t n) {
+    void* p = nullptr;
+    CHK(dev_alloc(&p, n * sizeof(T)));
+    *dst = static_cast<T*>(p);
+    if (n) HIPCHK(hipMemcpy(p, src, n * sizeof(T), hipMemcpyHostToDevice));
+    return NEGF_OK;
+}
+
+static negf_status build_impl(const negf_grid* g, int32_t R, const double* v, const negf_kb* kb,
+                              const double* capl, const double* capr, negf_op* op) {
+    if (!g || !v || !capl || !capr) {
+        set_error("null argument");
+        return NEGF_E_INVALID_ARG;
+    }
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1 || !(g->h > 0.0) || !std::isfinite(g->h)) {
+        set_error("invalid grid (%d x %d x %d, h=%g)", g->nx, g->ny, g->nz, g->h);
+        return NEGF_E_INVALID_ARG;
+    }
+    if (R < 1 || R > 6) {
+        set_error("stencil radius %d outside 1..6", R);
+        return NEGF_E_INVALID_ARG;
+    }
+    const int64_t N = (int64_t)g->nx * g->ny * g->nz;
+    if (N > (int64_t)1 << 31) {
+        set_error("grid too large");
+        return NEGF_E_INVALID_ARG;
+    }
+    for (int64_t i = 0; i < N; ++i)
+        if (!std::isfinite(v[i])) {
+            set_error("v_local[%lld] is not finite", (long long)i);
+            return NEGF_E_INVALID_ARG;
+        }
+    op->nx = g->nx; op->ny = g->ny; op->nz = g->nz; op->h = g->h; op->R = R; op->N = N;
+    CHK(plane_run(capl, g->nz, true, &op->zl0, &op->zl1));
+    CHK(plane_run(capr, g->nz, false, &op->zr0, &op->zr1));
+    if (op->zl1 > op->zr0) {
+        set_error("left and right CAP supports overlap");
+        return NEGF_E_INVALID_ARG;
+    }
+    if (op->zl1 - op->zl0 < R || op->zr1 - op->zr0 < R) {
+        set_error("each CAP must cover at least R=%d planes", R);
+        return NEGF_E_INVALID_ARG;
+    }
+    op->cap_l.assign(capl, capl + g->nz);
+    op->cap_r.assign(capr, capr + g->nz);
+    double c[7] = {0};
+    fd_weights(R, c);
+    const double inv2h2 = 1.0 / (2.0 * g->h * g->h);
+    op->coef.a[0] = 3.0 * c[0] * inv2h2;
+    for (int m = 1; m <= 6; ++m) op->coef.a[m] = (m <= R) ? c[m] * inv2h2 : 0.0;
+
+    // projectors
+    std::vector<int> pts, pt_off, pt_proj;
+    std::vector<double> pt_val;
+    if (kb && kb->n_proj > 0) {
+        if (!kb->offsets || !kb->idx || !kb->val || !kb->e_kb || kb->offsets[0] != 0) {
+            set_error("invalid projector arrays");
+            return NEGF_E_INVALID_ARG;
+        }
+        const int P = kb->n_proj;
+        for (int p = 0; p < P; ++p) {
+            if (kb->offsets[p + 1] < kb->offsets[p]) {
+                set_error("projector offsets decrease at %d", p);
+                return NEGF_E_INVALID_ARG;
+            }
+            if (!std::isfinite(kb->e_kb[p])) {
+                set_error("projector energy %d not finite", p);
+                return NEGF_E_INVALID_ARG;
+            }
+        }
+        const int64_t nnz = kb->offsets[P];
+        const int64_t plane = (int64_t)g->nx * g->ny;
+        std::map<int, std::vector<std::pair<int, double>>> by_pt;
+        int max_sup = 0;
+        for (int p = 0; p < P; ++p) {
+            max_sup = std::max<int>(max_sup, (int)(kb->offsets[p + 1] - kb->offsets[p]));
+            for (int64_t k = kb->offsets[p]; k < kb->offsets[p + 1]; ++k) {
+                const int i = kb->idx[k];
+                if (i < 0 || i >= N || !std::isfinite(kb->val[k])) {
+                    set_error("projector entry %lld invalid", (long long)k);
+                    return NEGF_E_INVALID_ARG;
+                }
+                const int z = (int)(i / plane);
+                if (capl[z] > 0.0 || capr[z] > 0.0) {
+                    set_error("projector %d reaches CAP plane %d", p, z);
+                    return NEGF_E_INVALID_ARG;
+                }
+                by_pt[i].push_back({p, kb->e_kb[p] * kb->val[k]});
+            }
+        }
+        pt_off.push_back(0);
+        for (auto& kv : by_pt) {
+            pts.push_back(kv.first);
+            for (auto& e : kv.second) {
+                pt_proj.push_back(e.first);
+                pt_val.push_back(e.second);
+            }
+            pt_off.push_back((int)pt_proj.size());
+        }
+        op->kb.n_proj = P;
+        op->kb.nnz = nnz;
+        op->kb.max_support = max_sup;
+        op->kb.n_pts = (int)pts.size();
+    }
+    // every argument is valid: device work starts here
+    if (hipGetDevice(&op->device) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("no HIP device");
+        return NEGF_E_DEVICE;
+    }
+    if (op->kb.n_proj > 0) {
+        const int P = kb->n_proj;
+        const int64_t nnz = kb->offsets[P];
+        CHK(upload(&op->kb.off, kb->offsets, (size_t)P + 1));
+        CHK(upload(&op->kb.idx, kb->idx, (size_t)nnz));
+        CHK(upload(&op->kb.val, kb->val, (size_t)nnz));
+        std::vector<float> vf(kb->val, kb->val + nnz);
+        CHK(upload(&op->kb.valf, vf.data(), vf.size()));
+        CHK(upload(&op->kb.e, kb->e_kb, (size_t)P));
+        CHK(upload(&op->kb.pts, pts.data(), pts.size()));
+        CHK(upload(&op->kb.pt_off, pt_off.data(), pt_off.size()));
+        CHK(upload(&op->kb.pt_proj, pt_proj.data(), pt_proj.size()));
+        CHK(upload(&op->kb.pt_val, pt_val.data(), pt_val.size()));
+    }
+    CHK(upload(&op->d_v, v, (size_t)N));
+    std::vector<double> wz(g->nz);
+    for (int z = 0; z < g->nz; ++z) wz[z] = capl[z] + capr[z];
+    CHK(upload(&op->d_wz, wz.data(), wz.size()));
+    CHK(upload(&op->d_wl, capl, (size_t)g->nz));
+    CHK(upload(&op->d_wr, capr, (size_t)g->nz));
+    HIPCHK(hipStreamCreateWithFlags(&op->own_stream, hipStreamNonBlocking));
+    op->bufs.resize(WS_COUNT);
+    return NEGF_OK;
+}
+
+extern "C" negf_status negf_build_operator(const negf_grid* g, int32_t stencil_radius,
+                                           const double* v_local, const negf_kb* kb,
+                                           const double* cap_left_z, const double* cap_right_z,
+                                           negf_op** out) {
+    g_last_error.clear();
+    if (!out) {
+        set_error("null output pointer");
+        return NEGF_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    negf_op* op = new negf_op();
+    op->device = -1;
+    negf_status s = build_impl(g, stencil_radius, v_local, kb, cap_left_z, cap_right_z, op);
+    if (s != NEGF_OK) {
+        free_op(op);
+        return s;
+    }
+    *out = op;
+    return NEGF_OK;
+}
+
+extern "C" void negf_destroy(negf_op* op) { free_op(op); }
+
+extern "C" const char* negf_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char* negf_version(void) { return "libnegf 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+// operator apply (standalone entry point)
+// ---------------------------------------------------------------------------
+__global__ void k_d2f(const double2* a, float2* b, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
+}
+__global__ void k_f2d(const float2* a, double2* b, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) b[i] = make_double2((double)a[i].x, (double)a[i].y);
+}
+
+extern "C" negf_status negf_apply_operator(negf_op* op, int32_t precision, int32_t n_vec,
+                                           const double* shifts, const negf_c64* x, negf_c64* y) {
+    g_last_error.clear();
+    if (!op || !shifts || !x || !y || n_vec < 1 || (precision != NEGF_FP64 && precision != NEGF_MIXED)) {
+        set_error("invalid argument to negf_apply_operator");
+        return NEGF_E_INVALID_ARG;
+    }
+    HIPCHK(hipSetDevice(op->device));
+    hipStream_t s = op->own_stream;
+    const int64_t N = op->N, tot = N * n_vec;
+    const bool dx = is_device_ptr(x), dy = is_device_ptr(y);
+    double2 *bx = nullptr, *by = nullptr, *kbc = nullptr;
+    double* sh = nullptr;
+    CHK(ws(op, WS_X64, (size_t)tot, &bx));
+    CHK(ws(op, WS_Q64, (size_t)tot, &by));
+    CHK(ws(op, WS_SHIFT, (size_t)n_vec, &sh));
+    CHK(ws(op, WS_KBC, (size_t)n_vec * std::max(1, op->kb.n_proj), &kbc));
+    HIPCHK(hipMemcpyAsync(bx, x, tot * sizeof(double2), dx ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(sh, shifts, n_vec * sizeof(double), hipMemcpyHostToDevice, s));
+    if (precision == NEGF_FP64) {
+        launch_apply<double>(op, bx, by, n_vec, sh, nullptr, kbc, s);
+    } else {
+        float2 *fx = nullptr, *fy = nullptr;
+        CHK(ws(op, WS_R, (size_t)tot, &fx));
+        CHK(ws(op, WS_Q, (size_t)tot, &fy));
+        const unsigned nb = (unsigned)((tot + 255) / 256);
+        hipLaunchKernelGGL(k_d2f, dim3(nb), dim3(256), 0, s, bx, fx, tot);
+        launch_apply<float>(op, fx, fy, n_vec, sh, nullptr, kbc, s);
+        hipLaunchKernelGGL(k_f2d, dim3(nb), dim3(256), 0, s, fy, by, tot);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(y, by, tot * sizeof(double2), dy ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return NEGF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// shared pieces of the solver drivers
+// ---------------------------------------------------------------------------
+struct Defaults {
+    int precision, core, direction, max_iter, block_width, shift_group, max_refine;
+    double tol;
+};
+
+static negf_status read_opts(const negf_opts* o, Defaults* d) {
+    d->precision = o ? o->precision : NEGF_FP64;
+    d->core = o ? o->core : NEGF_CORE_AUTO;
+    d->direction = o ? o->direction : NEGF_DIR_RL;
+    d->tol = (o && o->tol > 0) ? o->tol : 1e-10;
+    d->max_iter = (o && o->max_iter > 0) ? o->max_iter : 20000;
+    d->block_width = (o && o->block_width > 0) ? o->block_width : 0;
+    d->shift_group = (o && o->shift_group > 0) ? o->shift_group : 0;
+    d->max_refine = (o && o->max_refine > 0) ? o->max_refine : 8;
+    if (d->precision != NEGF_FP64 && d->precision != NEGF_MIXED) {
+        set_error("unknown precision %d", d->precision);
+        return NEGF_E_INVALID_ARG;
+    }
+    if (d->core < NEGF_CORE_AUTO || d->core > NEGF_CORE_MULTISHIFT) {
+        set_error("unknown core %d", d->core);
+        return NEGF_E_INVALID_ARG;
+    }
+    if (d->direction != NEGF_DIR_RL && d->direction != NEGF_DIR_LR) {
+        set_error("unknown direction %d", d->direction);
+        return NEGF_E_INVALID_ARG;
+    }
+    if (!(d->tol < 1.0) || !std::isfinite(d->tol)) {
+        set_error("tol must be in (0, 1)");
+        return NEGF_E_INVALID_ARG;
+    }
+    return NEGF_OK;
+}
+
+// the multi-shift core stores every Krylov residual on the requested rows
+static constexpr int kChunkIters = 32;
+
+static negf_status ensure_vchunks(negf_op* op, int slots_needed, int w, int n_rows,
+                                  double2*** d_tab, hipStream_t s) {
+    const size_t chunk_bytes = (size_t)kChunkIters * w * n_rows * sizeof(double2);
+    // drop chunks of a different geometry
+    if (!op->vchunks.empty() && op->vchunks[0].bytes != chunk_bytes) {
+        HIPCHK(hipStreamSynchronize(s));
+        for (auto& b : op->vchunks)
+            if (b.ptr) (void)hipFree(b.ptr);
+        op->vchunks.clear();
+    }
+    const int need = (slots_needed + kChunkIters - 1) / kChunkIters;
+    bool grew = false;
+    while ((int)op->vchunks.size() < need) {
+        Buffer b;
+        CHK(dev_alloc(&b.ptr, chunk_bytes));
+        b.bytes = chunk_bytes;
+        op->vchunks.push_back(b);
+        grew = true;
+    }
+    const int cap = std::max<int>(need, (int)op->vchunks.size());
+    double2** tab = nullptr;
+    CHK(ws(op, WS_CHUNKTAB, (size_t)std::max(cap, 1024), &tab));
+    if (grew || need > 0) {
+        std::vector<double2*> h(op->vchunks.size());
+        for (size_t i = 0; i < h.size(); ++i) h[i] = (double2*)op->vchunks[i].ptr;
+        HIPCHK(hipMemcpyAsync(tab, h.data(), h.size() * sizeof(double2*), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    *d_tab = tab;
+    return NEGF_OK;
+}
+
+static negf_status make_state(negf_op* op, int w, int ng, int max_iter, double tol, bool hist,
+                              IterState* st) {
+    // one allocation carved into the state arrays
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
+    const size_t o_k = take(w * sizeof(int)), o_done = take(w * sizeof(int));
+    const size_t o_rho = take(w * sizeof(double2)), o_alpha = take(w * sizeof(double2));
+    const size_t o_beta = take(w * sizeof(double2)), o_bn = take(w * sizeof(double));
+    const size_t o_rn = take(w * sizeof(double));
+    const size_t o_ah = hist ? take((size_t)w * max_iter * sizeof(double2)) : 0;
+    const size_t o_bh = hist ? take((size_t)w * max_iter * sizeof(double2)) : 0;
+    const size_t o_sh = hist ? take((size_t)w * (max_iter + 1) * sizeof(double)) : 0;
+    const size_t o_pi = ng ? take((size_t)w * ng * sizeof(double2)) : 0;
+    const size_t o_pp = ng ? take((size_t)w * ng * sizeof(double2)) : 0;
+    const size_t o_dl = ng ? take((size_t)w * ng * sizeof(double)) : 0;
+    const size_t o_sc = ng ? take((size_t)w * ng * sizeof(int)) : 0;
+    unsigned char* base = nullptr;
+    CHK(ws(op, WS_STATE, off, &base));
+    st->w = w;
+    st->ng = ng;
+    st->max_iter = max_iter;
+    st->tol = tol;
+    st->k = (int*)(base + o_k);
+    st->done = (int*)(base + o_done);
+    st->rho = (double2*)(base + o_rho);
+    st->alpha = (double2*)(base + o_alpha);
+    st->beta = (double2*)(base + o_beta);
+    st->bnorm = (double*)(base + o_bn);
+    st->rnorm = (double*)(base + o_rn);
+    st->a_hist = hist ? (double2*)(base + o_ah) : nullptr;
+    st->b_hist = hist ? (double2*)(base + o_bh) : nullptr;
+    st->s_hist = hist ? (double*)(base + o_sh) : nullptr;
+    st->pih = ng ? (double2*)(base + o_pi) : nullptr;
+    st->pih_prev = ng ? (double2*)(base + o_pp) : nullptr;
+    st->deltas = ng ? (double*)(base + o_dl) : nullptr;
+    st->sconv = ng ? (int*)(base + o_sc) : nullptr;
+    return NEGF_OK;
+}
+
+// Output of one multi-shift block.
+struct MSOut {
+    // transmission mode
+    double* h_tcol = nullptr;   // [w][ng] host
+    // column mode
+    double2* d_out = nullptr;   // device destination of X
+    int64_t out_col_stride = 0, out_shift_stride = 0;
+    // diagnostics (host, [w] and [w][ng])
+    int* h_iters = nullptr;
+    int* h_status = nullptr;
+    double* h_resid = nullptr;  // [w][ng]
+};
+
+// One block of w columns through the multi-shift core (FP64).
+//   cols (host) unit right-hand sides, or d_rhs (device [w][N]) dense ones
+//   rows: contiguous [row0, row0+n_rows) when d_rows == null
+static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, const int* cols,
+                                        const double2* d_rhs, const double* energies, int ng,
+                                        const int* d_rows, int64_t row0, int n_rows,
+                                        const double* d_row_w, const double* h_col_w,
+                                        const MSOut& out, int64_t* total_iters, hipStream_t s) {
+    const int64_t N = op->N;
+    const int nblk = part_blocks(N);
+    double2 *r, *p, *q, *part, *kbc;
+    double *part_nn, *shift;
+    int* d_cols;
+    CHK(ws(op, WS_R, (size_t)w * N, &r));
+    CHK(ws(op, WS_P, (size_t)w * N, &p));
+    CHK(ws(op, WS_Q, (size_t)w * N, &q));
+    CHK(ws(op, WS_PART, (size_t)w * nblk, &part));
+    CHK(ws(op, WS_PART2, (size_t)w * nblk, &part_nn));
+    CHK(ws(op, WS_KBC, (size_t)w * std::max(1, op->kb.n_proj), &kbc));
+    CHK(ws(op, WS_SHIFT, (size_t)w, &shift));
+    CHK(ws(op, WS_COLJ, (size_t)w, &d_cols));
+    IterState st;
+    CHK(make_state(op, w, ng, d.max_iter, d.tol, true, &st));
+
+    // seed: the highest energy of the group (usually the slowest system)
+    double e_seed = energies[0];
+    for (int g = 0; g < ng; ++g) e_seed = std::max(e_seed, energies[g]);
+    std::vector<double> h_shift(w, e_seed), h_delta((size_t)w * ng);
+    for (int c = 0; c < w; ++c)
+        for (int g = 0; g < ng; ++g) h_delta[(size_t)c * ng + g] = energies[g] - e_seed;
+    HIPCHK(hipMemcpyAsync(shift, h_shift.data(), w * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(st.deltas, h_delta.data(), h_delta.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    if (cols) {
+        HIPCHK(hipMemcpyAsync(d_cols, cols, w * sizeof(int), hipMemcpyHostToDevice, s));
+        launch_init_unit<double>(r, nullptr, N, w, d_cols, s);
+    } else {
+        HIPCHK(hipMemcpyAsync(r, d_rhs, (size_t)w * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    }
+    launch_norms<double>(r, N, w, nullptr, part, part_nn, s);
+    launch_reduce_init(part, part_nn, nblk, st, nullptr, s);
+    double2** tab = nullptr;
+    CHK(ensure_vchunks(op, kChunkIters, w, n_rows, &tab, s));
+    launch_store_rows<double>(r, N, w, d_rows, row0, n_rows, tab, kChunkIters, st, 0, s);
+    HIPCHK(hipGetLastError());
+
+    std::vector<int> h_done(w), h_k(w);
+    int k_host = 0;
+    const int chunk = 16;
+    while (true) {
+        const int steps = std::min(chunk, d.max_iter - k_host);
+        CHK(ensure_vchunks(op, k_host + steps + 2, w, n_rows, &tab, s));
+        for (int it = 0; it < steps; ++it) {
+            launch_p_update<double>(r, p, st, N, s);
+            launch_apply<double>(op, p, q, w, shift, st.done, kbc, s);
+            launch_dot_pq<double>(p, q, part, st, N, s);
+            launch_reduce_alpha(part, nblk, st, s);
+            launch_r_update<double>(r, q, nullptr, nullptr, part, part_nn, st, N, s);
+            launch_store_rows<double>(r, N, w, d_rows, row0, n_rows, tab, kChunkIters, st, 1, s);
+            launch_reduce_beta_multishift(part, part_nn, nblk, st, s);
+        }
+        HIPCHK(hipGetLastError());
+        k_host += steps;
+        HIPCHK(hipMemcpyAsync(h_done.data(), st.done, w * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        bool all = true;
+        for (int c = 0; c < w; ++c) all = all && h_done[c] != 0;
+        if (all || k_host >= d.max_iter) break;
+    }
+    // columns still running at max_iter
+    HIPCHK(hipMemcpyAsync(h_k.data(), st.k, w * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int m_max = 1;
+    for (int c = 0; c < w; ++c) {
+        m_max = std::max(m_max, h_k[c]);
+        *total_iters += h_k[c];
+        if (out.h_iters) out.h_iters[c] = h_k[c];
+        if (out.h_status) out.h_status[c] = h_done[c] ? h_done[c] - 1 : NEGF_ITEM_MAX_ITER;
+    }
+    // coefficients of the stored basis for every energy
+    double2 *gamma, *tri;
+    double* resid;
+    CHK(ws(op, WS_GAMMA, (size_t)w * m_max * ng, &gamma));
+    CHK(ws(op, WS_TRI, (size_t)w * m_max * 4 * ng, &tri));
+    CHK(ws(op, WS_MISC, (size_t)w * ng, &resid));
+    launch_tridiag_solve(st, st.k, gamma, m_max, tri, resid, s);
+    if (out.h_tcol) {
+        const int n_tiles = (n_rows + 63) / 64;
+        double *tpart, *tcol, *col_w;
+        CHK(ws(op, WS_TPART, (size_t)w * n_tiles * ng, &tpart));
+        CHK(ws(op, WS_TCOL, (size_t)w * ng + w, &tcol));
+        col_w = tcol + (size_t)w * ng;
+        HIPCHK(hipMemcpyAsync(col_w, h_col_w, w * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_gemm_reduce(tab, kChunkIters, w, n_rows, st.k, gamma, m_max, ng, d_row_w, tpart, s);
+        launch_sum_tpart(tpart, n_tiles, w, ng, col_w, tcol, s);
+        HIPCHK(hipMemcpyAsync(out.h_tcol, tcol, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (out.d_out) {
+        launch_gemm_store(tab, kChunkIters, w, n_rows, st.k, gamma, m_max, ng, out.d_out,
+                          out.out_col_stride, out.out_shift_stride, s);
+    }
+    if (out.h_resid)
+        HIPCHK(hipMemcpyAsync(out.h_resid, resid, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return NEGF_OK;
+}
+
+// launchers of adjoint.hip
+void launch_gather(const double2* x, int64_t N, int w, const int* rows, int n_rows,
+                   const int64_t* dst, double2* out, hipStream_t s);
+void launch_adjoint_rhs(const double2* g, int64_t N, int64_t plane, int w, const double* wl,
+                        double2* rhs, hipStream_t s);
+void launch_field(const double2* g, const double2* lam, int64_t N, int w, const double* colw,
+                  double scale, double* field, hipStream_t s);
+
+// One block of w (column, energy) items through the per-energy core with
+// FP64 iterative refinement.  The inner COCG runs in R (double for the FP64
+// path, float for the mixed path); x, the true residual r = b - A x, its norm
+// and the solution update x += ||r|| d are FP64.  On return the solutions are
+// in the WS_X64 workspace ([w][N] FP64).
+struct PEOut {
+    int* h_iters = nullptr;    // [w] Krylov iterations summed over refinement steps
+    int* h_status = nullptr;   // [w]
+    double* h_resid = nullptr; // [w] final true relative residual
+    int* h_refine = nullptr;   // [w] refinement steps
+};
+
+template <typename R>
+static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, const int* cols,
+                                        const double2* d_rhs, const double* item_e,
+                                        const PEOut& out, int64_t* total_iters, hipStream_t s) {
+    const int64_t N = op->N;
+    const int nblk = part_blocks(N);
+    cplx_t<R> *r, *p, *q, *dsol;
+    double2 *b64, *x64, *r64, *q64, *part, *kbc;
+    double *part_nn, *shift, *misc;
+    int* d_cols;
+    CHK(ws(op, WS_R, (size_t)w * N, &r));
+    CHK(ws(op, WS_P, (size_t)w * N, &p));
+    CHK(ws(op, WS_Q, (size_t)w * N, &q));
+    CHK(ws(op, WS_X, (size_t)w * N, &dsol));
+    CHK(ws(op, WS_B, (size_t)w * N, &b64));
+    CHK(ws(op, WS_X64, (size_t)w * N, &x64));
+    CHK(ws(op, WS_R64, (size_t)w * N, &r64));
+    CHK(ws(op, WS_Q64, (size_t)w * N, &q64));
+    CHK(ws(op, WS_PART, (size_t)w * nblk, &part));
+    CHK(ws(op, WS_PART2, (size_t)w * nblk, &part_nn));
+    CHK(ws(op, WS_KBC, (size_t)w * std::max(1, op->kb.n_proj), &kbc));
+    CHK(ws(op, WS_SHIFT, (size_t)w, &shift));
+    CHK(ws(op, WS_COLJ, (size_t)w, &d_cols));
+    CHK(ws(op, WS_MISC, (size_t)w * 4, &misc));
+    double* nu = misc;             // [w] current ||r64||
+    double* bn64 = misc + w;       // [w] ||b||
+    double* resid = misc + 2 * w;  // [w]
+    int* odone = (int*)(misc + 3 * w);
+    IterState st;
+    CHK(make_state(op, w, 0, d.max_iter, d.tol, false, &st));
+
+    HIPCHK(hipMemcpyAsync(shift, item_e, w * sizeof(double), hipMemcpyHostToDevice, s));
+    if (cols) {
+        HIPCHK(hipMemcpyAsync(d_cols, cols, w * sizeof(int), hipMemcpyHostToDevice, s));
+        launch_init_unit<double>(b64, nullptr, N, w, d_cols, s);
+    } else {
+        HIPCHK(hipMemcpyAsync(b64, d_rhs, (size_t)w * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    }
+    HIPCHK(hipMemsetAsync(x64, 0, (size_t)w * N * sizeof(double2), s));
+    HIPCHK(hipMemsetAsync(odone, 0, w * sizeof(int), s));
+    // x = 0: r64 = b, nu = ||b||
+    HIPCHK(hipMemcpyAsync(r64, b64, (size_t)w * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    launch_norms<double>(r64, N, w, nullptr, part, part_nn, s);
+    launch_reduce_residual(part_nn, nblk, w, odone, nullptr, nu, d.tol, resid, s);
+    HIPCHK(hipMemcpyAsync(bn64, nu, w * sizeof(double), hipMemcpyDeviceToDevice, s));
+
+    std::vector<int> h_done(w), h_odone(w), h_k(w), iters(w, 0), refine(w, 0);
+    int outer = 0;
+    const double inner_tol = (sizeof(R) == 8) ? 0.5 * d.tol : 2e-6;
+    while (true) {
+        if (outer > 0) {
+            launch_apply<double>(op, x64, q64, w, shift, odone, kbc, s);
+            launch_residual(b64, q64, r64, N, w, odone, part_nn, s);
+            launch_reduce_residual(part_nn, nblk, w, odone, bn64, nu, d.tol, resid, s);
+        }
+        HIPCHK(hipMemcpyAsync(h_odone.data(), odone, w * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        bool all = true;
+        for (int c = 0; c < w; ++c) all = all && h_odone[c];
+        if (all || outer >= d.max_refine) break;
+        ++outer;
+        for (int c = 0; c < w; ++c)
+            if (!h_odone[c]) ++refine[c];
+        // inner solve A d = r64 / ||r64|| in precision R
+        launch_scale_convert<R>(r64, r, dsol, N, w, odone, nu, s);
+        launch_norms<R>(r, N, w, odone, part, part_nn, s);
+        launch_reduce_init(part, part_nn, nblk, st, odone, s);
+        int k_host = 0;
+        while (true) {
+            const int steps = std::min(16, d.max_iter - k_host);
+            for (int it = 0; it < steps; ++it) {
+                launch_p_update<R>(r, p, st, N, s);
+                launch_apply<R>(op, p, q, w, shift, st.done, kbc, s);
+                launch_dot_pq<R>(p, q, part, st, N, s);
+                launch_reduce_alpha(part, nblk, st, s);
+                launch_r_update<R>(r, q, p, dsol, part, part_nn, st, N, s);
+                launch_reduce_beta_single(part, part_nn, nblk, st, inner_tol, s);
+            }
+            HIPCHK(hipGetLastError());
+            k_host += steps;
+            HIPCHK(hipMemcpyAsync(h_done.data(), st.done, w * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            bool alld = true;
+            for (int c = 0; c < w; ++c) alld = alld && h_done[c];
+            if (alld || k_host >= d.max_iter) break;
+        }
+        HIPCHK(hipMemcpyAsync(h_k.data(), st.k, w * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int c = 0; c < w; ++c)
+            if (!h_odone[c]) iters[c] += h_k[c];
+        launch_accumulate<R>(x64, dsol, N, w, odone, nu, s);
+    }
+    for (int c = 0; c < w; ++c) {
+        *total_iters += iters[c];
+        if (out.h_iters) out.h_iters[c] = iters[c];
+        if (out.h_status) out.h_status[c] = h_odone[c] ? NEGF_ITEM_CONVERGED : NEGF_ITEM_MAX_ITER;
+        if (out.h_refine) out.h_refine[c] = refine[c];
+    }
+    if (out.h_resid)
+        HIPCHK(hipMemcpyAsync(out.h_resid, resid, w * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return NEGF_OK;
+}
+
+static negf_status run_per_energy(negf_op* op, const Defaults& d, int w, const int* cols,
+                                  const double2* d_rhs, const double* item_e, const PEOut& out,
+                                  int64_t* total_iters, hipStream_t s) {
+    if (d.precision == NEGF_MIXED)
+        return run_per_energy_block<float>(op, d, w, cols, d_rhs, item_e, out, total_iters, s);
+    return run_per_energy_block<double>(op, d, w, cols, d_rhs, item_e, out, total_iters, s);
+}
+
+// ---------------------------------------------------------------------------
+// source / row sets of the transmission (Eq. 7)
+// ---------------------------------------------------------------------------
+struct Sides {
+    std::vector<int> cols;   // source grid indices (CAP support, ascending)
+    std::vector<double> colw; // 4 W_src at the column
+    int64_t row0 = 0;        // rows: contiguous CAP support of the other side
+    int n_rows = 0;
+    std::vector<double> roww;
+};
+
+static void make_sides(const negf_op* op, int direction, Sides* sd) {
+    const int64_t plane = (int64_t)op->nx * op->ny;
+    const bool rl = direction == NEGF_DIR_RL;
+    const int cz0 = rl ? op->zr0 : op->zl0, cz1 = rl ? op->zr1 : op->zl1;
+    const int rz0 = rl ? op->zl0 : op->zr0, rz1 = rl ? op->zl1 : op->zr1;
+    const std::vector<double>& wc = rl ? op->cap_r : op->cap_l;
+    const std::vector<double>& wr = rl ? op->cap_l : op->cap_r;
+    for (int z = cz0; z < cz1; ++z)
+        for (int64_t i = 0; i < plane; ++i) {
+            sd->cols.push_back((int)(z * plane + i));
+            sd->colw.push_back(4.0 * wc[z]);
+        }
+    sd->row0 = rz0 * plane;
+    sd->n_rows = (int)((rz1 - rz0) * plane);
+    for (int z = rz0; z < rz1; ++z)
+        for (int64_t i = 0; i < plane; ++i) sd->roww.push_back(wr[z]);
+}
+
+static negf_status check_energies(int n_e, const double* e) {
+    if (n_e < 1 || !e) {
+        set_error("need at least one energy");
+        return NEGF_E_INVALID_ARG;
+    }
+    for (int i = 0; i < n_e; ++i)
+        if (!std::isfinite(e[i])) {
+            set_error("energy %d not finite", i);
+            return NEGF_E_INVALID_ARG;
+        }
+    return NEGF_OK;
+}
+
+static int pick_core(const Defaults& d) {
+    if (d.core != NEGF_CORE_AUTO) return d.core;
+    return d.precision == NEGF_FP64 ? NEGF_CORE_MULTISHIFT : NEGF_CORE_PER_ENERGY;
+}
+
+static negf_status final_status(int n_bad, int n_break) {
+    if (n_break > 0) {
+        set_error("%d items broke down", n_break);
+        return NEGF_E_BREAKDOWN;
+    }
+    if (n_bad > 0) {
+        set_error("%d items did not converge", n_bad);
+        return NEGF_E_NOT_CONVERGED;
+    }
+    return NEGF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// negf_transmission
+// ---------------------------------------------------------------------------
+static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t n_e,
+                                     const double* energies, double* T, negf_diag* diag) {
+    Defaults d;
+    CHK(read_opts(opts, &d));
+    CHK(check_energies(n_e, energies));
+    if (!T) {
+        set_error("null T");
+        return NEGF_E_INVALID_ARG;
+    }
+    const int core = pick_core(d);
+    if (core == NEGF_CORE_MULTISHIFT && d.precision != NEGF_FP64) {
+        set_error("the multi-shift core runs in FP64 only (mixed precision uses the per-energy core)");
+        return NEGF_E_INVALID_ARG;
+    }
+    HIPCHK(hipSetDevice(op->device));
+    hipStream_t s = pick_stream(op, opts);
+    const auto t0 = std::chrono::steady_clock::now();
+    Sides sd;
+    make_sides(op, d.direction, &sd);
+    const int n_cols = (int)sd.cols.size();
+    double* d_roww = nullptr;
+    CHK(ws(op, WS_ROWW, (size_t)sd.n_rows, &d_roww));
+    HIPCHK(hipMemcpyAsync(d_roww, sd.roww.data(), sd.n_rows * sizeof(double), hipMemcpyHostToDevice, s));
+    // tcol[e][c]
+    std::vector<double> tcol((size_t)n_e * n_cols, 0.0);
+    std::vector<int> iters((size_t)n_e * n_cols, 0), status((size_t)n_e * n_cols, 0);
+    std::vector<double> resid((size_t)n_e * n_cols, 0.0);
+    int64_t total_iters = 0;
+    if (core == NEGF_CORE_MULTISHIFT) {
+        const int ng_max = d.shift_group ? std::min(d.shift_group, n_e) : n_e;
+        const int wmax = d.block_width ? d.block_width : 64;
+        std::vector<double> blk_t, blk_r;
+        std::vector<int> blk_it, blk_st;
+        for (int g0 = 0; g0 < n_e; g0 += ng_max) {
+            const int ng = std::min(ng_max, n_e - g0);
+            for (int c0 = 0; c0 < n_cols; c0 += wmax) {
+                const int w = std::min(wmax, n_cols - c0);
+                blk_t.assign((size_t)w * ng, 0.0);
+                blk_r.assign((size_t)w * ng, 0.0);
+                blk_it.assign(w, 0);
+                blk_st.assign(w, 0);
+                MSOut mo;
+                mo.h_tcol = blk_t.data();
+                mo.h_iters = blk_it.data();
+                mo.h_status = blk_st.data();
+                mo.h_resid = blk_r.data();
+                CHK(run_multishift_block(op, d, w, sd.cols.data() + c0, nullptr, energies + g0, ng,
+                                         nullptr, sd.row0, sd.n_rows, d_roww, sd.colw.data() + c0,
+                                         mo, &total_iters, s));
+                for (int c = 0; c < w; ++c)
+                    for (int g = 0; g < ng; ++g) {
+                        const size_t o = (size_t)(g0 + g) * n_cols + c0 + c;
+                        tcol[o] = blk_t[(size_t)c * ng + g];
+                        resid[o] = blk_r[(size_t)c * ng + g];
+                        iters[o] = blk_it[c];
+                        // a column that hit max_iter can still have converged
+                        // energies; judge each by its own residual estimate
+                        status[o] = (blk_st[c] == NEGF_ITEM_BREAKDOWN) ? NEGF_ITEM_BREAKDOWN
+                                    : (resid[o] <= d.tol * 1.0000001 ? NEGF_ITEM_CONVERGED : NEGF_ITEM_MAX_ITER);
+                    }
+            }
+        }
+    } else {
+        const int wmax = d.block_width ? d.block_width : 64;
+        const int64_t n_items = (int64_t)n_e * n_cols;
+        std::vector<int> icol;
+        std::vector<double> ie, colw;
+        std::vector<int> b_it, b_st;
+        std::vector<double> b_res, b_t;
+        double* d_colw = nullptr;
+        double* d_t = nullptr;
+        CHK(ws(op, WS_TCOL, (size_t)2 * wmax, &d_colw));
+        d_t = d_colw + wmax;
+        for (int64_t i0 = 0; i0 < n_items; i0 += wmax) {
+            const int w = (int)std::min<int64_t>(wmax, n_items - i0);
+            icol.resize(w); ie.resize(w); colw.resize(w);
+            for (int c = 0; c < w; ++c) {
+                const int64_t it = i0 + c;
+                const int e = (int)(it / n_cols), j = (int)(it % n_cols);
+                icol[c] = sd.cols[j];
+                ie[c] = energies[e];
+                colw[c] = sd.colw[j];
+            }
+            b_it.assign(w, 0); b_st.assign(w, 0); b_res.assign(w, 0.0); b_t.assign(w, 0.0);
+            PEOut po;
+            po.h_iters = b_it.data();
+            po.h_status = b_st.data();
+            po.h_resid = b_res.data();
+            CHK(run_per_energy(op, d, w, icol.data(), nullptr, ie.data(), po, &total_iters, s));
+            double2* x64 = (double2*)op->bufs[WS_X64].ptr;
+            HIPCHK(hipMemcpyAsync(d_colw, colw.data(), w * sizeof(double), hipMemcpyHostToDevice, s));
+            launch_weighted_norm(x64, op->N, w, sd.row0, sd.n_rows, d_roww, d_colw, d_t, s);
+            HIPCHK(hipMemcpyAsync(b_t.data(), d_t, w * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (int c = 0; c < w; ++c) {
+                const size_t o = (size_t)(i0 + c);  // == e * n_cols + j
+                tcol[o] = b_t[c];
+                iters[o] = b_it[c];
+                status[o] = b_st[c];
+                resid[o] = b_res[c];
+            }
+        }
+    }
+    int n_bad = 0, n_break = 0;
+    for (int e = 0; e < n_e; ++e) {
+        double acc = 0.0;
+        for (int c = 0; c < n_cols; ++c) {
+            const size_t o = (size_t)e * n_cols + c;
+            acc += tcol[o];
+            if (status[o] == NEGF_ITEM_BREAKDOWN) ++n_break;
+            else if (status[o] != NEGF_ITEM_CONVERGED) ++n_bad;
+        }
+        T[e] = acc;
+    }
+    if (diag) {
+        const size_t n = (size_t)n_e * n_cols;
+        if (diag->iters) std::copy(iters.begin(), iters.end(), diag->iters);
+        if (diag->resid) std::copy(resid.begin(), resid.end(), diag->resid);
+        if (diag->t_col) std::copy(tcol.begin(), tcol.end(), diag->t_col);
+        if (diag->item_status) std::copy(status.begin(), status.end(), diag->item_status);
+        (void)n;
+        diag->total_iters = total_iters;
+        diag->n_not_converged = n_bad + n_break;
+        diag->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return final_status(n_bad, n_break);
+}
+
+extern "C" negf_status negf_transmission(negf_op* op, const negf_opts* opts, int32_t n_e,
+                                         const double* energies, double* T, negf_diag* diag) {
+    g_last_error.clear();
+    if (!op) {
+        set_error("null op");
+        return NEGF_E_INVALID_ARG;
+    }
+    return transmission_impl(op, opts, n_e, energies, T, diag);
+}
+
+// ---------------------------------------------------------------------------
+// negf_solve_columns
+// ---------------------------------------------------------------------------
+static negf_status solve_columns_impl(negf_op* op, const negf_opts* opts, int32_t n_e,
+                                      const double* energies, int32_t n_rhs, const int32_t* rhs_idx,
+                                      const negf_c64* rhs_dense, int32_t n_rows,
+                                      const int32_t* row_idx, negf_c64* out, int32_t* item_status) {
+    Defaults d;
+    CHK(read_opts(opts, &d));
+    CHK(check_energies(n_e, energies));
+    const int64_t N = op->N;
+    if (n_rhs < 1 || (!rhs_idx == !rhs_dense) || !out) {
+        set_error("need n_rhs >= 1, exactly one of rhs_idx / rhs_dense, and out");
+        return NEGF_E_INVALID_ARG;
+    }
+    if (!row_idx) n_rows = (int32_t)N;
+    if (n_rows < 1) {
+        set_error("n_rows must be >= 1");
+        return NEGF_E_INVALID_ARG;
+    }
+    if (rhs_idx)
+        for (int i = 0; i < n_rhs; ++i)
+            if (rhs_idx[i] < 0 || rhs_idx[i] >= N) {
+                set_error("rhs_idx[%d] out of range", i);
+                return NEGF_E_INVALID_ARG;
+            }
+    if (row_idx)
+        for (int i = 0; i < n_rows; ++i)
+            if (row_idx[i] < 0 || row_idx[i] >= N) {
+                set_error("row_idx[%d] out of range", i);
+                return NEGF_E_INVALID_ARG;
+            }
+    const int core = pick_core(d);
+    if (core == NEGF_CORE_MULTISHIFT && d.precision != NEGF_FP64) {
+        set_error("the multi-shift core runs in FP64 only (mixed precision uses the per-energy core)");
+        return NEGF_E_INVALID_ARG;
+    }
+    HIPCHK(hipSetDevice(op->device));
+    hipStream_t s = pick_stream(op, opts);
+    const size_t out_elems = (size_t)n_e * n_rhs * n_rows;
+    const bool out_dev = is_device_ptr(out);
+    double2* d_out = nullptr;
+    if (out_dev) {
+        d_out = (double2*)out;
+    } else {
+        CHK(ws(op, WS_TPART, out_elems, &d_out));
+    }
+    // right-hand sides on the device
+    double2* d_rhs_all = nullptr;
+    if (rhs_dense) {
+        if (is_device_ptr(rhs_dense)) {
+            d_rhs_all = (double2*)rhs_dense;
+        } else {
+            CHK(ws(op, WS_TCOL, (size_t)n_rhs * N, &d_rhs_all));
+            HIPCHK(hipMemcpyAsync(d_rhs_all, rhs_dense, (size_t)n_rhs * N * sizeof(double2), hipMemcpyHostToDevice, s));
+        }
+    }
+    int* d_rows = nullptr;
+    if (row_idx) {
+        CHK(ws(op, WS_ROWS, (size_t)n_rows, &d_rows));
+        HIPCHK(hipMemcpyAsync(d_rows, row_idx, n_rows * sizeof(int), hipMemcpyHostToDevice, s));
+    }
+    std::vector<int> status((size_t)n_e * n_rhs, 0);
+    int64_t total_iters = 0;
+    if (core == NEGF_CORE_MULTISHIFT) {
+        const int ng_max = d.shift_group ? std::min(d.shift_group, n_e) : n_e;
+        const int wmax = d.block_width ? d.block_width : 64;
+        std::vector<int> blk_st;
+        std::vector<double> blk_r;
+        for (int g0 = 0; g0 < n_e; g0 += ng_max) {
+            const int ng = std::min(ng_max, n_e - g0);
+            for (int c0 = 0; c0 < n_rhs; c0 += wmax) {
+                const int w = std::min(wmax, n_rhs - c0);
+                blk_st.assign(w, 0);
+                blk_r.assign((size_t)w * ng, 0.0);
+                MSOut mo;
+                mo.d_out = d_out + ((size_t)g0 * n_rhs + c0) * n_rows;
+                mo.out_col_stride = n_rows;
+                mo.out_shift_stride = (int64_t)n_rhs * n_rows;
+                mo.h_status = blk_st.data();
+                mo.h_resid = blk_r.data();
+                CHK(run_multishift_block(op, d, w, rhs_idx ? rhs_idx + c0 : nullptr,
+                                         d_rhs_all ? d_rhs_all + (size_t)c0 * N : nullptr,
+                                         energies + g0, ng, d_rows, 0, n_rows, nullptr, nullptr,
+                                         mo, &total_iters, s));
+                for (int c = 0; c < w; ++c)
+                    for (int g = 0; g < ng; ++g)
+                        status[(size_t)(g0 + g) * n_rhs + c0 + c] =
+                            (blk_st[c] == NEGF_ITEM_BREAKDOWN) ? NEGF_ITEM_BREAKDOWN
+                            : (blk_r[(size_t)c * ng + g] <= d.tol * 1.0000001 ? NEGF_ITEM_CONVERGED
+                                                                              : NEGF_ITEM_MAX_ITER);
+            }
+        }
+    } else {
+        const int wmax = d.block_width ? d.block_width : 64;
+        const int64_t n_items = (int64_t)n_e * n_rhs;
+        std::vector<int> icol, b_st;
+        std::vector<double> ie;
+        std::vector<int64_t> dst;
+        int64_t* d_dst = nullptr;
+        double2* d_rhs_blk = nullptr;
+        CHK(ws(op, WS_ROWW, (size_t)wmax, &d_dst));
+        for (int64_t i0 = 0; i0 < n_items; i0 += wmax) {
+            const int w = (int)std::min<int64_t>(wmax, n_items - i0);
+            icol.resize(w); ie.resize(w); dst.resize(w);
+            if (d_rhs_all) CHK(ws(op, WS_GAMMA, (size_t)w * N, &d_rhs_blk));
+            for (int c = 0; c < w; ++c) {
+                const int64_t it = i0 + c;  // e * n_rhs + r
+                const int e = (int)(it / n_rhs), rr = (int)(it % n_rhs);
+                ie[c] = energies[e];
+                dst[c] = it * n_rows;
+                if (rhs_idx) icol[c] = rhs_idx[rr];
+                else HIPCHK(hipMemcpyAsync(d_rhs_blk + (size_t)c * N, d_rhs_all + (size_t)rr * N,
+                                           N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+            }
+            std::vector<int> b_st2(w, 0);
+            PEOut po;
+            po.h_status = b_st2.data();
+            CHK(run_per_energy(op, d, w, rhs_idx ? icol.data() : nullptr, d_rhs_blk, ie.data(), po,
+                               &total_iters, s));
+            HIPCHK(hipMemcpyAsync(d_dst, dst.data(), w * sizeof(int64_t), hipMemcpyHostToDevice, s));
+            launch_gather((double2*)op->bufs[WS_X64].ptr, N, w, d_rows, n_rows, d_dst, d_out, s);
+            HIPCHK(hipStreamSynchronize(s));
+            for (int c = 0; c < w; ++c) status[(size_t)(i0 + c)] = b_st2[c];
+        }
+    }
+    if (!out_dev)
+        HIPCHK(hipMemcpyAsync(out, d_out, out_elems * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int n_bad = 0, n_break = 0;
+    for (size_t i = 0; i < status.size(); ++i) {
+        if (status[i] == NEGF_ITEM_BREAKDOWN) ++n_break;
+        else if (status[i] != NEGF_ITEM_CONVERGED) ++n_bad;
+        if (item_status) item_status[i] = status[i];
+    }
+    return final_status(n_bad, n_break);
+}
+
+extern "C" negf_status negf_solve_columns(negf_op* op, const negf_opts* opts, int32_t n_e,
+                                          const double* energies, int32_t n_rhs,
+                                          const int32_t* rhs_idx, const negf_c64* rhs_dense,
+                                          int32_t n_rows, const int32_t* row_idx, negf_c64* out,
+                                          int32_t* item_status) {
+    g_last_error.clear();
+    if (!op) {
+        set_error("null op");
+        return NEGF_E_INVALID_ARG;
+    }
+    return solve_columns_impl(op, opts, n_e, energies, n_rhs, rhs_idx, rhs_dense, n_rows, row_idx,
+                              out, item_status);
+}
+
+// ---------------------------------------------------------------------------
+// negf_transmission_grad
+// ---------------------------------------------------------------------------
+static negf_status grad_impl(negf_op* op, const negf_opts* opts, int32_t n_e,
+                             const double* energies, const double* weights, double* dL_dV,
+                             double* T) {
+    Defaults d;
+    CHK(read_opts(opts, &d));
+    CHK(check_energies(n_e, energies));
+    if (!weights || !dL_dV) {
+        set_error("null weights or dL_dV");
+        return NEGF_E_INVALID_ARG;
+    }
+    HIPCHK(hipSetDevice(op->device));
+    hipStream_t s = pick_stream(op, opts);
+    const int64_t N = op->N;
+    const int64_t plane = (int64_t)op->nx * op->ny;
+    Sides sd;
+    make_sides(op, NEGF_DIR_RL, &sd);
+    const int n_cols = (int)sd.cols.size();
+    const int wmax = d.block_width ? d.block_width : 32;
+    double *d_field, *d_colw, *d_roww, *d_t;
+    double2 *d_g, *d_rhs;
+    CHK(ws(op, WS_ROWS, (size_t)N, &d_field));
+    CHK(ws(op, WS_ROWW, (size_t)sd.n_rows, &d_roww));
+    CHK(ws(op, WS_TCOL, (size_t)2 * wmax, &d_colw));
+    d_t = d_colw + wmax;
+    CHK(ws(op, WS_GAMMA, (size_t)wmax * N, &d_g));
+    CHK(ws(op, WS_TRI, (size_t)wmax * N, &d_rhs));
+    HIPCHK(hipMemsetAsync(d_field, 0, N * sizeof(double), s));
+    HIPCHK(hipMemcpyAsync(d_roww, sd.roww.data(), sd.n_rows * sizeof(double), hipMemcpyHostToDevice, s));
+    int64_t total_iters = 0;
+    int n_bad = 0;
+    std::vector<double> ie, colw, tb;
+    for (int e = 0; e < n_e; ++e) {
+        double Te = 0.0;
+        if (weights[e] == 0.0 && !T) continue;
+        for (int c0 = 0; c0 < n_cols; c0 += wmax) {
+            const int w = std::min(wmax, n_cols - c0);
+            ie.assign(w, energies[e]);
+            colw.assign(sd.colw.begin() + c0, sd.colw.begin() + c0 + w);
+            tb.assign(w, 0.0);
+            std::vector<int> st1(w, 0), st2(w, 0);
+            PEOut po;
+            po.h_status = st1.data();
+            Defaults d64 = d;
+            d64.precision = NEGF_FP64;
+            // forward columns g_j
+            CHK(run_per_energy(op, d64, w, sd.cols.data() + c0, nullptr, ie.data(), po, &total_iters, s));
+            double2* x64 = (double2*)op->bufs[WS_X64].ptr;
+            HIPCHK(hipMemcpyAsync(d_g, x64, (size_t)w * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(d_colw, colw.data(), w * sizeof(double), hipMemcpyHostToDevice, s));
+            launch_weighted_norm(d_g, N, w, sd.row0, sd.n_rows, d_roww, d_colw, d_t, s);
+            HIPCHK(hipMemcpyAsync(tb.data(), d_t, w * sizeof(double), hipMemcpyDeviceToHost, s));
+            // adjoint right-hand sides W_L o conj(g_j) and solves with the same operator
+            launch_adjoint_rhs(d_g, N, plane, w, op->d_wl, d_rhs, s);
+            po.h_status = st2.data();
+            CHK(run_per_energy(op, d64, w, nullptr, d_rhs, ie.data(), po, &total_iters, s));
+            x64 = (double2*)op->bufs[WS_X64].ptr;
+            // 8 Re sum_j W_R,j g_j lambda_j = 2 Re sum_j (4 W_R,j) g_j lambda_j
+            launch_field(d_g, x64, N, w, d_colw, 2.0 * weights[e], d_field, s);
+            HIPCHK(hipStreamSynchronize(s));
+            for (int c = 0; c < w; ++c) {
+                Te += tb[c];
+                if (st1[c] != NEGF_ITEM_CONVERGED || st2[c] != NEGF_ITEM_CONVERGED) ++n_bad;
+            }
+        }
+        if (T) T[e] = Te;
+    }
+    HIPCHK(hipMemcpyAsync(dL_dV, d_field, N * sizeof(double),
+                          is_device_ptr(dL_dV) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return final_status(n_bad, 0);
+}
+
+extern "C" negf_status negf_transmission_grad(negf_op* op, const negf_opts* opts, int32_t n_e,
+                                              const double* energies, const double* weights,
+                                              double* dL_dV, double* T) {
+    g_last_error.clear();
+    if (!op) {
+        set_error("null op");
+        return NEGF_E_INVALID_ARG;
+    }
+    return grad_impl(op, opts, n_e, energies, weights, dL_dV, T);
+}

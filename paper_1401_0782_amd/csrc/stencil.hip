@@ -1,0 +1,297 @@
+// Operator apply Y = A(E_c) X on a block of complex vectors, for gfx950.
+//
+// A(E) = E*1 - H + i(W_L + W_R) with H = -1/2 Lap_h + diag(V) + sum_p E_p b_p b_p^T
+// (Sec. II.B-C).  The Laplacian is the order-2R star stencil with zero ghosts.
+//
+// Layout: a block holds w vectors, column-major: X[c][i], i = ix + nx*(iy + ny*iz),
+// complex interleaved (double2 / float2).
+//
+// Kernel design (memory bound, see the roofline in the design notes): one
+// work-group owns one column and a tile of TY full x-rows and marches along z.
+// The 2R+1 z-values of every output point it owns sit in a register queue;
+// each new plane is staged once in LDS (tile rows plus R halo rows on each
+// side, x padded by R zeros) so the 4R in-plane neighbours come from LDS.
+// HBM sees each input plane once per tile (halo rows are re-read through L2
+// by the neighbouring tile, which runs at the same z on the same XCD because
+// the tiles of one column are issued consecutively).
+#include "negf_internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename R> struct Coef { R a[7]; };
+
+template <typename R>
+__device__ inline cplx_t<R> cadd_t(cplx_t<R> a, cplx_t<R> b) {
+    cplx_t<R> r; r.x = a.x + b.x; r.y = a.y + b.y; return r;
+}
+
+// ---------------------------------------------------------------------------
+// reference-style kernel: one thread per (point, column), neighbours from
+// global memory.  Used for planes wider than the tiled kernel supports.
+// ---------------------------------------------------------------------------
+template <int RAD, typename R>
+__global__ __launch_bounds__(kThreads) void k_apply_direct(
+    const cplx_t<R>* __restrict__ x, cplx_t<R>* __restrict__ y, int nx, int ny, int nz,
+    Coef<R> cf, const double* __restrict__ v, const double* __restrict__ wz,
+    const double* __restrict__ shift, const int* __restrict__ skip) {
+    const int c = blockIdx.y;
+    if (skip && skip[c]) return;
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= N) return;
+    const int ix = (int)(i % nx);
+    const int64_t t = i / nx;
+    const int iy = (int)(t % ny);
+    const int iz = (int)(t / ny);
+    const cplx_t<R>* xc = x + (int64_t)c * N;
+    const cplx_t<R> xi = xc[i];
+    const R dr = (R)(shift[c] - v[i] + (double)cf.a[0]);
+    const R di = (R)wz[iz];
+    R accx = dr * xi.x - di * xi.y;
+    R accy = dr * xi.y + di * xi.x;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+#pragma unroll
+    for (int m = 1; m <= RAD; ++m) {
+        R sx_ = 0, sy_ = 0;
+        if (ix - m >= 0) { sx_ += xc[i - m].x; sy_ += xc[i - m].y; }
+        if (ix + m < nx) { sx_ += xc[i + m].x; sy_ += xc[i + m].y; }
+        if (iy - m >= 0) { sx_ += xc[i - m * sy].x; sy_ += xc[i - m * sy].y; }
+        if (iy + m < ny) { sx_ += xc[i + m * sy].x; sy_ += xc[i + m * sy].y; }
+        if (iz - m >= 0) { sx_ += xc[i - m * sz].x; sy_ += xc[i - m * sz].y; }
+        if (iz + m < nz) { sx_ += xc[i + m * sz].x; sy_ += xc[i + m * sz].y; }
+        accx += cf.a[m] * sx_;
+        accy += cf.a[m] * sy_;
+    }
+    cplx_t<R> o; o.x = accx; o.y = accy;
+    y[(int64_t)c * N + i] = o;
+}
+
+// ---------------------------------------------------------------------------
+// tiled z-marching kernel
+//   work-group: one column c, rows [y0, y0+TY) of every plane, z in [z0, z1)
+//   thread t owns the points (x = t % nx, y = y0 + t / nx + k*(256/nx)), k < PPT
+// ---------------------------------------------------------------------------
+template <int RAD, typename R, int PPT>
+__global__ __launch_bounds__(kThreads) void k_apply_tiled(
+    const cplx_t<R>* __restrict__ x, cplx_t<R>* __restrict__ y, int nx, int ny, int nz,
+    int ty, int n_ytiles, int zchunk, Coef<R> cf, const double* __restrict__ v,
+    const double* __restrict__ wz, const double* __restrict__ shift,
+    const int* __restrict__ skip) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx_t<R>* tile = reinterpret_cast<cplx_t<R>*>(smem_raw);
+    const int bid = blockIdx.x;
+    const int c = blockIdx.y;
+    if (skip && skip[c]) return;
+    const int ytile = bid % n_ytiles;
+    const int zc = bid / n_ytiles;
+    const int z0 = zc * zchunk;
+    const int z1 = min(nz, z0 + zchunk);
+    const int y0 = ytile * ty;
+    const int rows = min(ty, ny - y0);
+    const int pitch = nx + 2 * RAD;           // LDS row pitch (x padded)
+    const int lrows = rows + 2 * RAD;         // LDS rows (y halo)
+    const int64_t plane = (int64_t)nx * ny;
+    const int64_t N = plane * nz;
+    const cplx_t<R>* xc = x + (int64_t)c * N;
+    cplx_t<R>* yc = y + (int64_t)c * N;
+    const int tid = threadIdx.x;
+    const int rows_per_pass = kThreads / nx;  // threads beyond rows_per_pass*nx idle
+    const int lx = tid % nx;
+    const int ly0 = (tid < rows_per_pass * nx) ? tid / nx : (1 << 20);
+    const double e_c = shift[c] + (double)cf.a[0];
+
+    // zero the LDS tile (padding stays zero)
+    for (int k = tid; k < pitch * lrows; k += kThreads) { tile[k].x = 0; tile[k].y = 0; }
+
+    // register queue: q[k][d] = value at (point k, plane z + d - RAD)
+    cplx_t<R> q[PPT][2 * RAD + 1];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int yy = ly0 + k * rows_per_pass;
+#pragma unroll
+        for (int d = 0; d < 2 * RAD + 1; ++d) {
+            const int zz = z0 + d - RAD;
+            cplx_t<R> val; val.x = 0; val.y = 0;
+            if (yy < rows && zz >= 0 && zz < nz && d < 2 * RAD)
+                val = xc[(int64_t)zz * plane + (int64_t)(y0 + yy) * nx + lx];
+            q[k][d] = val;
+        }
+    }
+    __syncthreads();
+
+    for (int z = z0; z < z1; ++z) {
+        // lead plane z + RAD into the queue tail
+        const int zl = z + RAD;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int yy = ly0 + k * rows_per_pass;
+            cplx_t<R> val; val.x = 0; val.y = 0;
+            if (yy < rows && zl < nz) val = xc[(int64_t)zl * plane + (int64_t)(y0 + yy) * nx + lx];
+            q[k][2 * RAD] = val;
+        }
+        // stage plane z: interior rows from the queue, halo rows from memory
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int yy = ly0 + k * rows_per_pass;
+            if (yy < rows) tile[(yy + RAD) * pitch + RAD + lx] = q[k][RAD];
+        }
+        for (int k = tid; k < 2 * RAD * nx; k += kThreads) {
+            const int hr = k / nx;         // 0 .. 2R-1
+            const int hx = k % nx;
+            const int yy = hr < RAD ? (hr - RAD) : (rows + hr - RAD);  // tile-relative row
+            const int gy = y0 + yy;
+            cplx_t<R> val; val.x = 0; val.y = 0;
+            if (gy >= 0 && gy < ny) val = xc[(int64_t)z * plane + (int64_t)gy * nx + hx];
+            tile[(yy + RAD) * pitch + RAD + hx] = val;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int yy = ly0 + k * rows_per_pass;
+            if (yy < rows) {
+                const int64_t gi = (int64_t)z * plane + (int64_t)(y0 + yy) * nx + lx;
+                const cplx_t<R> xi = q[k][RAD];
+                const R dr = (R)(e_c - v[gi]);
+                const R di = (R)wz[z];
+                R ax = dr * xi.x - di * xi.y;
+                R ay = dr * xi.y + di * xi.x;
+                const cplx_t<R>* row = tile + (yy + RAD) * pitch + RAD + lx;
+#pragma unroll
+                for (int m = 1; m <= RAD; ++m) {
+                    const cplx_t<R> a0 = row[-m], a1 = row[m];
+                    const cplx_t<R> b0 = row[-m * pitch], b1 = row[m * pitch];
+                    const cplx_t<R> c0 = q[k][RAD - m], c1 = q[k][RAD + m];
+                    ax += cf.a[m] * ((a0.x + a1.x) + (b0.x + b1.x) + (c0.x + c1.x));
+                    ay += cf.a[m] * ((a0.y + a1.y) + (b0.y + b1.y) + (c0.y + c1.y));
+                }
+                cplx_t<R> o; o.x = ax; o.y = ay;
+                yc[gi] = o;
+            }
+        }
+        __syncthreads();
+        // shift the queue
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+            for (int d = 0; d < 2 * RAD; ++d) q[k][d] = q[k][d + 1];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// separable projectors: gather c[col][p] = b_p^T x_col, then
+// y[col][i] -= sum_{p touching i} E_p b_p(i) c[col][p]
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_kb_gather(
+    const cplx_t<R>* __restrict__ x, int64_t N, const int64_t* __restrict__ off,
+    const int* __restrict__ idx, const double* __restrict__ val, int n_proj, int w,
+    double2* __restrict__ out, const int* __restrict__ skip) {
+    // one wave per (projector, column)
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int p = blockIdx.x;
+    const int c = blockIdx.y * (kThreads / 64) + wave;
+    if (c >= w) return;
+    if (skip && skip[c]) return;
+    const cplx_t<R>* xc = x + (int64_t)c * N;
+    double sx = 0, sy = 0;
+    for (int64_t k = off[p] + lane; k < off[p + 1]; k += 64) {
+        const cplx_t<R> xv = xc[idx[k]];
+        const double b = val[k];
+        sx += b * (double)xv.x;
+        sy += b * (double)xv.y;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        sx += __shfl_xor(sx, o, 64);
+        sy += __shfl_xor(sy, o, 64);
+    }
+    if (lane == 0) out[(int64_t)c * n_proj + p] = make_double2(sx, sy);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_kb_scatter(
+    cplx_t<R>* __restrict__ y, int64_t N, const int* __restrict__ pts,
+    const int* __restrict__ pt_off, const int* __restrict__ pt_proj,
+    const double* __restrict__ pt_val, int n_pts, int n_proj,
+    const double2* __restrict__ cproj, const int* __restrict__ skip) {
+    const int c = blockIdx.y;
+    if (skip && skip[c]) return;
+    const int k = blockIdx.x * kThreads + threadIdx.x;
+    if (k >= n_pts) return;
+    double sx = 0, sy = 0;
+    const double2* cc = cproj + (int64_t)c * n_proj;
+    for (int e = pt_off[k]; e < pt_off[k + 1]; ++e) {
+        const double2 cv = cc[pt_proj[e]];
+        const double f = pt_val[e];
+        sx += f * cv.x;
+        sy += f * cv.y;
+    }
+    cplx_t<R>* yc = y + (int64_t)c * N;
+    cplx_t<R> o = yc[pts[k]];
+    o.x -= (R)sx;
+    o.y -= (R)sy;
+    yc[pts[k]] = o;
+}
+
+template <int RAD, typename R>
+void apply_dispatch(const negf_op* op, const cplx_t<R>* x, cplx_t<R>* y, int w,
+                    const double* d_shift, const int* d_skip, hipStream_t s) {
+    Coef<R> cf;
+    for (int m = 0; m < 7; ++m) cf.a[m] = (R)op->coef.a[m];
+    const int nx = op->nx, ny = op->ny, nz = op->nz;
+    const bool tiled = (nx >= 8) && (nx <= kThreads);
+    if (tiled) {
+        const int rows_per_pass = kThreads / nx;
+        // points per thread: 2 passes of rows per tile when the register budget allows
+        constexpr int PPT = (RAD >= 5 && sizeof(R) == 8) ? 1 : 2;
+        int ty = rows_per_pass * PPT;
+        if (ty > ny) ty = ny;
+        const int n_ytiles = (ny + ty - 1) / ty;
+        // z chunks: enough work-groups to fill the device, chunks >= 4R planes
+        int zchunk = nz;
+        const long target = 1024;
+        long wgs = (long)n_ytiles * w;
+        while (wgs * ((nz + zchunk - 1) / zchunk) < target && zchunk > 4 * RAD) zchunk = (zchunk + 1) / 2;
+        const int n_z = (nz + zchunk - 1) / zchunk;
+        const size_t lds = (size_t)(nx + 2 * RAD) * (ty + 2 * RAD) * sizeof(cplx_t<R>);
+        dim3 grid(n_ytiles * n_z, w);
+        hipLaunchKernelGGL((k_apply_tiled<RAD, R, PPT>), grid, dim3(kThreads), lds, s, x, y, nx,
+                           ny, nz, ty, n_ytiles, zchunk, cf, op->d_v, op->d_wz, d_shift, d_skip);
+    } else {
+        const int64_t N = op->N;
+        dim3 grid((unsigned)((N + kThreads - 1) / kThreads), w);
+        hipLaunchKernelGGL((k_apply_direct<RAD, R>), grid, dim3(kThreads), 0, s, x, y, nx, ny,
+                           nz, cf, op->d_v, op->d_wz, d_shift, d_skip);
+    }
+}
+
+}  // namespace
+
+template <typename R>
+void launch_apply(const negf_op* op, const cplx_t<R>* x, cplx_t<R>* y, int w,
+                  const double* d_shift, const int* d_skip, double2* d_kbc, hipStream_t s) {
+    switch (op->R) {
+        case 1: apply_dispatch<1, R>(op, x, y, w, d_shift, d_skip, s); break;
+        case 2: apply_dispatch<2, R>(op, x, y, w, d_shift, d_skip, s); break;
+        case 3: apply_dispatch<3, R>(op, x, y, w, d_shift, d_skip, s); break;
+        case 4: apply_dispatch<4, R>(op, x, y, w, d_shift, d_skip, s); break;
+        case 5: apply_dispatch<5, R>(op, x, y, w, d_shift, d_skip, s); break;
+        default: apply_dispatch<6, R>(op, x, y, w, d_shift, d_skip, s); break;
+    }
+    if (op->kb.n_proj > 0) {
+        const DeviceKB& kb = op->kb;
+        dim3 g1(kb.n_proj, (w + 3) / 4);
+        hipLaunchKernelGGL((k_kb_gather<R>), g1, dim3(kThreads), 0, s, x, op->N, kb.off, kb.idx,
+                           kb.val, kb.n_proj, w, d_kbc, d_skip);
+        dim3 g2((kb.n_pts + kThreads - 1) / kThreads, w);
+        hipLaunchKernelGGL((k_kb_scatter<R>), g2, dim3(kThreads), 0, s, y, op->N, kb.pts,
+                           kb.pt_off, kb.pt_proj, kb.pt_val, kb.n_pts, kb.n_proj, d_kbc, d_skip);
+    }
+}
+
+template void launch_apply<double>(const negf_op*, const double2*, double2*, int, const double*,
+                                   const int*, double2*, hipStream_t);
+template void launch_apply<float>(const negf_op*, const float2*, float2*, int, const double*,
+                                  const int*, double2*, hipStream_t);

@@ -1,0 +1,97 @@
+"""Host-side checks of the C ABI library (no GPU needed)."""
+
+import ctypes as C
+import pathlib
+import re
+
+import numpy as np
+import pytest
+
+ROOT = pathlib.Path(__file__).resolve().parents[1]
+
+
+def _header_functions():
+    text = (ROOT / "include" / "negf.h").read_text()
+    return sorted(set(re.findall(r"\b(negf_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    from paper_1401_0782_amd import _abi
+
+    lib = _abi.load()
+    declared = _header_functions()
+    assert set(declared) == set(_abi.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert lib.negf_version().decode().startswith("libnegf")
+
+
+def _build(**kw):
+    import paper_1401_0782_amd as P
+    from workloads import make_wire
+
+    w = make_wire(1)
+    args = dict(nx=w.nx, ny=w.ny, nz=w.nz, h=w.h, stencil_radius=w.R, v_local=w.v_local,
+                cap_left_z=w.cap_left, cap_right_z=w.cap_right)
+    args.update(kw)
+    return P.negf_build_operator(**args)
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(stencil_radius=0), "radius"),
+    (dict(stencil_radius=7), "radius"),
+    (dict(h=0.0), "grid"),
+    (dict(h=-1.0), "grid"),
+])
+def test_invalid_operator_arguments_rejected_before_device(bad, msg):
+    from paper_1401_0782_amd import NegfError
+    from paper_1401_0782_amd._abi import NEGF_E_INVALID_ARG
+
+    with pytest.raises(NegfError) as ei:
+        _build(**bad)
+    assert ei.value.status == NEGF_E_INVALID_ARG and msg in str(ei.value)
+
+
+def test_invalid_caps_rejected():
+    from paper_1401_0782_amd import NegfError
+    from workloads import make_wire
+
+    w = make_wire(1)
+    bad = w.cap_left.copy()
+    bad[3] = -0.1
+    for kw in (dict(cap_left_z=bad),
+               dict(cap_left_z=np.zeros(w.nz)),
+               dict(cap_left_z=np.r_[w.cap_left[:1] * 0, w.cap_left[1:]]),  # not touching wall
+               dict(cap_left_z=np.r_[[0.5] * 20, [0.0] * 12], cap_right_z=np.r_[[0.0] * 12, [0.5] * 20]),
+               dict(cap_left_z=np.r_[[0.5], [0.0] * 31]),  # fewer than R planes
+               ):
+        with pytest.raises(NegfError):
+            _build(**kw)
+
+
+def test_nan_potential_rejected():
+    from paper_1401_0782_amd import NegfError
+    from workloads import make_wire
+
+    v = make_wire(1).v_local.copy()
+    v[5] = np.nan
+    with pytest.raises(NegfError, match="not finite"):
+        _build(v_local=v)
+
+
+def test_projector_on_cap_plane_rejected():
+    from paper_1401_0782_amd import NegfError
+
+    with pytest.raises(NegfError, match="CAP plane"):
+        _build(kb_offsets=np.array([0, 1]), kb_idx=np.array([3]), kb_val=np.array([1.0]),
+               kb_energy=np.array([0.2]))
+
+
+def test_null_output_rejected():
+    from paper_1401_0782_amd import _abi
+
+    lib = _abi.load()
+    g = _abi.negf_grid(4, 4, 8, 0.5)
+    assert lib.negf_build_operator(C.byref(g), 2, None, None, None, None, None) == _abi.NEGF_E_INVALID_ARG
+    assert b"null" in lib.negf_last_error()
+    lib.negf_destroy(None)  # no-op

@@ -1,0 +1,119 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import make_custom, make_wire, rhs_columns, left_support
+
+pytestmark = pytest.mark.gpu
+
+
+def _op(wire):
+    import paper_1401_0782_amd as P
+
+    return P.operator_from_wire(wire)
+
+
+def _small_kb_wire(nx=9, ny=7, nz=40, R=3, h=0.5):
+    # two atoms with s+p projectors, away from the 6-plane CAPs
+    cx, cy = (nx + 1) * h / 2, (ny + 1) * h / 2
+    wells = [(cx + 0.3, cy - 0.2, 7.5, 0.4), (cx - 0.4, cy + 0.3, 12.0, 0.5)]
+    return make_custom(nx, ny, nz, h, R, 6, np.linspace(0.2, 1.2, 6), wells=wells,
+                       atoms_kb=[(0.8, 0.3, 0.1), (0.7, 0.2, 0.15)], name="kbwire")
+
+
+@pytest.mark.parametrize("R,shape", [(1, (5, 3, 12)), (2, (8, 8, 32)), (3, (13, 6, 20)),
+                                     (4, (24, 5, 30)), (5, (7, 40, 22)), (6, (32, 9, 26))])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_apply_matches_oracle(gpu_lib, R, shape, prec):
+    import paper_1401_0782_amd as P
+
+    nx, ny, nz = shape
+    rng = np.random.default_rng([7, R, nx])
+    wire = make_custom(nx, ny, nz, 0.45, R, max(R, 3), [0.3],
+                       wells=[((nx + 1) * 0.225, (ny + 1) * 0.225, (nz + 1) * 0.225, 0.5)])
+    op = _op(wire)
+    H = O.hamiltonian(wire)
+    n_vec = 5
+    shifts = rng.uniform(-1, 1, n_vec)
+    X = rng.standard_normal((n_vec, wire.N)) + 1j * rng.standard_normal((n_vec, wire.N))
+    Y = P.negf_apply_operator(op, shifts, X, precision=P.NEGF_FP64 if prec == "fp64" else P.NEGF_MIXED)
+    for c in range(n_vec):
+        A = O.operator_A(wire, shifts[c], H)
+        ref = A @ X[c]
+        err = np.linalg.norm(Y[c] - ref) / np.linalg.norm(ref)
+        assert err <= (1e-13 if prec == "fp64" else 2e-6), (c, err)
+
+
+def test_apply_with_projectors(gpu_lib):
+    import paper_1401_0782_amd as P
+
+    wire = _small_kb_wire()
+    op = _op(wire)
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((3, wire.N)) + 1j * rng.standard_normal((3, wire.N))
+    sh = np.array([0.1, 0.5, 0.9])
+    Y = P.negf_apply_operator(op, sh, X)
+    H = O.hamiltonian(wire)
+    for c in range(3):
+        ref = O.operator_A(wire, sh[c], H) @ X[c]
+        assert np.linalg.norm(Y[c] - ref) / np.linalg.norm(ref) < 1e-13
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    w = make_wire(1)
+    return w, O.transmission(w, method="dense")
+
+
+@pytest.mark.parametrize("core", ["multishift", "per_energy"])
+def test_cfg1_fp64(gpu_lib, cfg1, core):
+    import paper_1401_0782_amd as P
+
+    w, Tref = cfg1
+    op = _op(w)
+    c = P.NEGF_CORE_MULTISHIFT if core == "multishift" else P.NEGF_CORE_PER_ENERGY
+    T, diag = P.negf_transmission(op, w.energies, n_cols=len(rhs_columns(w)), core=c, tol=1e-12)
+    print(core, T, Tref, diag.total_iters)
+    assert np.max(np.abs(T - Tref)) <= 1e-8
+
+
+def test_cfg1_mixed(gpu_lib, cfg1):
+    import paper_1401_0782_amd as P
+
+    w, Tref = cfg1
+    op = _op(w)
+    T, diag = P.negf_transmission(op, w.energies, n_cols=len(rhs_columns(w)),
+                                  precision=P.NEGF_MIXED, tol=1e-10)
+    print("mixed", T, Tref, diag.total_iters)
+    assert np.max(np.abs(T - Tref)) <= 1e-6
+    assert np.all(diag.resid <= 1e-10)
+
+
+def test_kb_wire_transmission(gpu_lib):
+    import paper_1401_0782_amd as P
+
+    w = _small_kb_wire()
+    Tref = O.transmission(w, method="dense")
+    op = _op(w)
+    T = P.negf_transmission(op, w.energies, tol=1e-12)
+    print(T, Tref)
+    assert np.max(np.abs(T - Tref)) <= 1e-8
+
+
+def test_solve_columns_match_oracle(gpu_lib):
+    import paper_1401_0782_amd as P
+
+    w = _small_kb_wire()
+    op = _op(w)
+    cols = rhs_columns(w)[[0, 17, 100]]
+    rows = left_support(w)[::7]
+    for core in (P.NEGF_CORE_MULTISHIFT, P.NEGF_CORE_PER_ENERGY):
+        out, st = P.negf_solve_columns(op, w.energies[:4], rhs_idx=cols, row_idx=rows, core=core,
+                                       tol=1e-12)
+        assert np.all(st == 0)
+        for e, E in enumerate(w.energies[:4]):
+            G = O.green_columns(w, E, cols, rows=rows, method="dense")
+            err = np.abs(out[e].T - G).max() / np.abs(G).max()
+            assert err < 1e-9, (core, e, err)
