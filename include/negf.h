@@ -102,6 +102,9 @@ typedef struct {
     int32_t block_width; /* columns (or items) per block; 0 -> auto */
     int32_t shift_group; /* energies per multi-shift run; 0 -> all */
     int32_t max_refine;  /* mixed: outer refinement steps; 0 -> 8 */
+    int32_t col_begin;   /* negf_transmission(_grad): first source column of the */
+    int32_t col_count;   /* shard to sum over (0 -> all); T is then that shard's
+                            partial sum, which shards add up to the full T(E) */
     void* stream;        /* hipStream_t or NULL */
 } negf_opts;
 
@@ -116,6 +119,13 @@ typedef struct {
     int64_t total_iters;     /* out: sum of Krylov iterations over runs */
     int32_t n_not_converged; /* out */
     double seconds;          /* out: wall time of the device work */
+    int32_t time_matvec;     /* in: nonzero brackets every fused stencil launch with
+                                HIP events on the work stream */
+    double matvec_seconds;   /* out: summed duration of those launches */
+    int64_t matvec_launches; /* out: number of stencil launches timed */
+    double matvec_bytes;     /* out: algorithmic HBM bytes of those launches: per
+                                active column r and p_{k-1} read, p_k and q written
+                                (16 B per point in FP64, 8 B in FP32), plus V once */
 } negf_diag;
 
 typedef struct negf_op negf_op;

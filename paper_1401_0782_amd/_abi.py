@@ -47,14 +47,17 @@ class negf_kb(C.Structure):
 class negf_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("core", C.c_int32), ("direction", C.c_int32),
                 ("tol", C.c_double), ("max_iter", C.c_int32), ("block_width", C.c_int32),
-                ("shift_group", C.c_int32), ("max_refine", C.c_int32), ("stream", C.c_void_p)]
+                ("shift_group", C.c_int32), ("max_refine", C.c_int32), ("col_begin", C.c_int32),
+                ("col_count", C.c_int32), ("stream", C.c_void_p)]
 
 
 class negf_diag(C.Structure):
     _fields_ = [("iters", C.POINTER(C.c_int32)), ("resid", C.POINTER(C.c_double)),
                 ("t_col", C.POINTER(C.c_double)), ("item_status", C.POINTER(C.c_int32)),
                 ("total_iters", C.c_int64), ("n_not_converged", C.c_int32),
-                ("seconds", C.c_double)]
+                ("seconds", C.c_double), ("time_matvec", C.c_int32),
+                ("matvec_seconds", C.c_double), ("matvec_launches", C.c_int64),
+                ("matvec_bytes", C.c_double)]
 
 
 _lib = None

@@ -117,10 +117,11 @@ def operator_from_wire(wire) -> Operator:
 
 
 def _opts(precision=NEGF_FP64, core=NEGF_CORE_AUTO, direction=NEGF_DIR_RL, tol=0.0,
-          max_iter=0, block_width=0, shift_group=0, max_refine=0, stream=None):
+          max_iter=0, block_width=0, shift_group=0, max_refine=0, col_begin=0, col_count=0,
+          stream=None):
     return _abi.negf_opts(int(precision), int(core), int(direction), float(tol), int(max_iter),
-                          int(block_width), int(shift_group), int(max_refine),
-                          C.c_void_p(stream) if stream else None)
+                          int(block_width), int(shift_group), int(max_refine), int(col_begin),
+                          int(col_count), C.c_void_p(stream) if stream else None)
 
 
 def negf_apply_operator(op: Operator, shifts, x, precision=NEGF_FP64):
@@ -156,22 +157,28 @@ def n_source_columns(op: Operator, cap_src) -> int:
     return int(np.count_nonzero(np.asarray(cap_src) > 0)) * op.nx * op.ny
 
 
-def negf_transmission(op: Operator, energies, n_cols: Optional[int] = None, check=True, **opts):
-    """T(E) (FP64) for the given energies.  n_cols (number of source columns)
-    enables the per-item diagnostics."""
+def negf_transmission(op: Operator, energies, n_cols: Optional[int] = None, check=True,
+                      time_matvec=False, **opts):
+    """T(E) (FP64) for the given energies.  n_cols (number of source columns
+    in the shard, see col_begin/col_count) enables the per-item diagnostics;
+    time_matvec brackets the stencil launches with HIP events."""
     energies = np.ascontiguousarray(energies, dtype=np.float64)
     n_e = energies.size
     T = np.zeros(n_e)
     o = _opts(**opts)
     d = None
     arrays = None
-    if n_cols:
-        arrays = (np.zeros((n_e, n_cols), np.int32), np.zeros((n_e, n_cols)),
-                  np.zeros((n_e, n_cols)), np.zeros((n_e, n_cols), np.int32))
-        d = _abi.negf_diag(arrays[0].ctypes.data_as(C.POINTER(C.c_int32)),
-                           arrays[1].ctypes.data_as(C.POINTER(C.c_double)),
-                           arrays[2].ctypes.data_as(C.POINTER(C.c_double)),
-                           arrays[3].ctypes.data_as(C.POINTER(C.c_int32)), 0, 0, 0.0)
+    if n_cols or time_matvec:
+        nc = max(1, n_cols or 0)
+        arrays = (np.zeros((n_e, nc), np.int32), np.zeros((n_e, nc)),
+                  np.zeros((n_e, nc)), np.zeros((n_e, nc), np.int32))
+        ptrs = [None] * 4
+        if n_cols:
+            ptrs = [arrays[0].ctypes.data_as(C.POINTER(C.c_int32)),
+                    arrays[1].ctypes.data_as(C.POINTER(C.c_double)),
+                    arrays[2].ctypes.data_as(C.POINTER(C.c_double)),
+                    arrays[3].ctypes.data_as(C.POINTER(C.c_int32))]
+        d = _abi.negf_diag(*ptrs, 0, 0, 0.0, 1 if time_matvec else 0, 0.0, 0, 0.0)
     st = _lib().negf_transmission(op.handle, C.byref(o), n_e, _ptr(energies), _ptr(T),
                                   C.byref(d) if d is not None else None)
     if check:
@@ -180,6 +187,8 @@ def negf_transmission(op: Operator, energies, n_cols: Optional[int] = None, chec
         return T
     diag = Diagnostics(arrays[0], arrays[1], arrays[2], arrays[3], int(d.total_iters),
                        int(d.n_not_converged), float(d.seconds), int(st))
+    diag.extra.update(matvec_seconds=float(d.matvec_seconds),
+                      matvec_launches=int(d.matvec_launches), matvec_bytes=float(d.matvec_bytes))
     return T, diag
 
 

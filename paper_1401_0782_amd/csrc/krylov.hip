@@ -103,7 +103,8 @@ __global__ __launch_bounds__(kT) void k_dot(const cplx_t<R>* __restrict__ a,
 
 // alpha = rho / (p^T q) per column
 __global__ __launch_bounds__(kT) void k_reduce_alpha(const double2* __restrict__ part, int nblk,
-                                                     IterState st) {
+                                                     IterState st, const double2* __restrict__ kbc,
+                                                     const double* __restrict__ e_kb, int n_proj) {
     __shared__ double lds[2 * kT / 64];
     const int c = blockIdx.x;
     if (st.done[c]) return;
@@ -112,6 +113,15 @@ __global__ __launch_bounds__(kT) void k_reduce_alpha(const double2* __restrict__
         const double2 v = part[(int64_t)c * nblk + b];
         s[0] += v.x;
         s[1] += v.y;
+    }
+    // projector part of p^T A p: -sum_p E_p (b_p^T p)^2 (bilinear, no conjugation)
+    if (kbc) {
+        for (int q = threadIdx.x; q < n_proj; q += kT) {
+            const double2 cv = kbc[(int64_t)c * n_proj + q];
+            const double2 c2 = cmul(cv, cv);
+            s[0] -= e_kb[q] * c2.x;
+            s[1] -= e_kb[q] * c2.y;
+        }
     }
     block_sum<2>(s, lds);
     if (threadIdx.x == 0) {
@@ -178,7 +188,7 @@ __global__ __launch_bounds__(kT) void k_reduce_beta_ms(const double2* __restrict
                                                        const double* __restrict__ part_nn,
                                                        int nblk, IterState st) {
     __shared__ double lds[3 * kT / 64];
-    __shared__ double2 sh_sc[4];
+    __shared__ double2 sh_sc[6];
     __shared__ int sh_all;
     const int c = blockIdx.x;
     if (st.done[c]) return;
@@ -209,6 +219,8 @@ __global__ __launch_bounds__(kT) void k_reduce_beta_ms(const double2* __restrict
         sh_sc[1] = ck;
         sh_sc[2] = make_double2(sk / snew, skm1 / snew);
         sh_sc[3] = make_double2(snew, cfinite(beta) ? 1.0 : 0.0);
+        sh_sc[4] = beta;
+        sh_sc[5] = make_double2(sh[0] / sk, 0.0);
         st.rho[c] = rho_new;
         st.beta[c] = beta;
         st.rnorm[c] = snew;
@@ -217,13 +229,21 @@ __global__ __launch_bounds__(kT) void k_reduce_beta_ms(const double2* __restrict
     __syncthreads();
     const double2 a = sh_sc[0], ck = sh_sc[1];
     const double r1 = sh_sc[2].x, r2 = sh_sc[2].y;
+    const double2 beta = sh_sc[4];
+    const double s0_over_sk = sh_sc[5].x;
+    double2* rec = st.rec + ((int64_t)c * st.chunk + k % st.chunk) * 3 * st.ng;
     int all = 1;
     for (int g = threadIdx.x; g < st.ng; g += kT) {
         const int64_t o = (int64_t)c * st.ng + g;
-        // A shift whose residual met tol keeps its flag: shifts far from the
-        // seed keep converging geometrically and their pih would overflow.
-        // The final coefficients come from the tridiagonal solve, not from pih.
-        if (st.sconv[o]) continue;
+        // A shift whose residual met tol is frozen: its iterate stays the
+        // converged one, and shifts far from the seed would otherwise keep
+        // converging geometrically until pih overflows.
+        if (st.sconv[o]) {
+            rec[g] = mk(0.0, 0.0);
+            rec[st.ng + g] = mk(0.0, 0.0);
+            rec[2 * st.ng + g] = mk(1.0, 0.0);
+            continue;
+        }
         const double d = st.deltas[o];
         const double2 pk = st.pih[o], pkm1 = st.pih_prev[o];
         // (1 + a d) pk + ck pk, scaled by s_k/s_{k+1}; minus ck pkm1 s_{k-1}/s_{k+1}
@@ -232,8 +252,16 @@ __global__ __launch_bounds__(kT) void k_reduce_beta_ms(const double2* __restrict
         const double2 pn = mk(r1 * t1.x - r2 * t2.x, r1 * t1.y - r2 * t2.y);
         st.pih_prev[o] = pk;
         st.pih[o] = pn;
+        // shifted COCG scalars: r^sigma_k = r_k / pi_k, alpha^sigma_k = (pi_k/pi_{k+1}) alpha_k,
+        // beta^sigma_k = (pi_k/pi_{k+1})^2 beta_k, with pi_k = pih_k s_k / s_0
+        const double2 inv_pi = cscale(s0_over_sk, cdiv(mk(1.0, 0.0), pk));
+        const double2 ratio = cscale(r1, cdiv(pk, pn));  // (pih_k s_k)/(pih_{k+1} s_{k+1})
+        rec[g] = inv_pi;
+        rec[st.ng + g] = cmul(ratio, a);
+        rec[2 * st.ng + g] = cmul(cmul(ratio, ratio), beta);
         const double res = 1.0 / sqrt(cabs2(pn));
-        if (res <= st.tol) st.sconv[o] = 1;
+        st.sres[o] = res;
+        if (res <= st.tol) st.sconv[o] = k + 1;  // iterate x_{k+1} converged
         else all = 0;
     }
     if (!all) atomicAnd(&sh_all, 0);
@@ -286,18 +314,18 @@ __global__ __launch_bounds__(kT) void k_reduce_beta_single(const double2* __rest
     }
 }
 
-// copy r[c][rows] into the stored-vector slot k[c] + slot_offset
+// copy r[c][rows] into ring slot (k[c] + slot_offset) mod ring_len
 template <typename R>
 __global__ __launch_bounds__(kT) void k_store_rows(const cplx_t<R>* __restrict__ r, int64_t N,
                                                    const int* __restrict__ rows, int64_t row0,
-                                                   int n_rows, double2* const* __restrict__ tab,
-                                                   int chunk_iters, int w,
+                                                   int n_rows, double2* __restrict__ ring,
+                                                   int ring_len, int w,
                                                    const int* __restrict__ done,
                                                    const int* __restrict__ kit, int slot_offset) {
     const int c = blockIdx.y;
     if (done[c]) return;
-    const int slot = kit[c] + slot_offset;
-    double2* dst = tab[slot / chunk_iters] + ((int64_t)(slot % chunk_iters) * w + c) * n_rows;
+    const int slot = (kit[c] + slot_offset) % ring_len;
+    double2* dst = ring + ((int64_t)slot * w + c) * n_rows;
     const cplx_t<R>* rc = r + (int64_t)c * N;
     for (int i = blockIdx.x * kT + threadIdx.x; i < n_rows; i += gridDim.x * kT) {
         const int64_t gi = rows ? (int64_t)rows[i] : row0 + i;
@@ -331,8 +359,10 @@ void launch_dot_pq(const cplx_t<R>* p, const cplx_t<R>* q, double2* part, const 
     hipLaunchKernelGGL((k_dot<R>), g, dim3(kT), 0, s, p, q, N, st.done, part);
 }
 
-void launch_reduce_alpha(const double2* part, int nblk, IterState st, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_alpha, dim3(st.w), dim3(kT), 0, s, part, nblk, st);
+void launch_reduce_alpha(const double2* part, int nblk, IterState st, hipStream_t s,
+                         const double2* kbc, const double* e_kb, int n_proj) {
+    hipLaunchKernelGGL(k_reduce_alpha, dim3(st.w), dim3(kT), 0, s, part, nblk, st, kbc, e_kb,
+                       n_proj);
 }
 
 template <typename R>
@@ -357,13 +387,13 @@ void launch_reduce_beta_single(const double2* part_rr, const double* part_nn, in
 
 template <typename R>
 void launch_store_rows(const cplx_t<R>* r, int64_t N, int w, const int* rows, int64_t row0,
-                       int n_rows, double2* const* chunk_tab, int chunk_iters,
-                       const IterState& st, int slot_offset, hipStream_t s) {
+                       int n_rows, double2* ring, int ring_len, const IterState& st,
+                       int slot_offset, hipStream_t s) {
     int gx = (n_rows + kT - 1) / kT;
     if (gx > 256) gx = 256;
     dim3 g(gx, w);
-    hipLaunchKernelGGL((k_store_rows<R>), g, dim3(kT), 0, s, r, N, rows, row0, n_rows, chunk_tab,
-                       chunk_iters, w, st.done, st.k, slot_offset);
+    hipLaunchKernelGGL((k_store_rows<R>), g, dim3(kT), 0, s, r, N, rows, row0, n_rows, ring,
+                       ring_len, w, st.done, st.k, slot_offset);
 }
 
 #define INST(R)                                                                                  \
@@ -374,7 +404,7 @@ void launch_store_rows(const cplx_t<R>* r, int64_t N, int w, const int* rows, in
     template void launch_r_update<R>(cplx_t<R>*, const cplx_t<R>*, cplx_t<R>*, cplx_t<R>*,      \
                                      double2*, double*, const IterState&, int64_t, hipStream_t); \
     template void launch_store_rows<R>(const cplx_t<R>*, int64_t, int, const int*, int64_t, int, \
-                                       double2* const*, int, const IterState&, int, hipStream_t);
+                                       double2*, int, const IterState&, int, hipStream_t);
 INST(double)
 INST(float)
 #undef INST
@@ -455,6 +485,7 @@ __global__ __launch_bounds__(kT) void k_reduce_init(const double2* __restrict__ 
             st.pih[(int64_t)c * st.ng + g] = make_double2(1.0, 0.0);
             st.pih_prev[(int64_t)c * st.ng + g] = make_double2(1.0, 0.0);
             st.sconv[(int64_t)c * st.ng + g] = 0;
+            st.sres[(int64_t)c * st.ng + g] = 1.0;
         }
     }
 }

@@ -187,8 +187,6 @@ static void free_op(negf_op* op) {
         if (p) (void)hipFree(p);
     for (auto& b : op->bufs)
         if (b.ptr) (void)hipFree(b.ptr);
-    for (auto& b : op->vchunks)
-        if (b.ptr) (void)hipFree(b.ptr);
     if (op->own_stream) (void)hipStreamDestroy(op->own_stream);
     delete op;
 }
@@ -409,6 +407,7 @@ extern "C" negf_status negf_apply_operator(negf_op* op, int32_t precision, int32
 // ---------------------------------------------------------------------------
 struct Defaults {
     int precision, core, direction, max_iter, block_width, shift_group, max_refine;
+    int col_begin, col_count;
     double tol;
 };
 
@@ -421,6 +420,12 @@ static negf_status read_opts(const negf_opts* o, Defaults* d) {
     d->block_width = (o && o->block_width > 0) ? o->block_width : 0;
     d->shift_group = (o && o->shift_group > 0) ? o->shift_group : 0;
     d->max_refine = (o && o->max_refine > 0) ? o->max_refine : 8;
+    d->col_begin = o ? o->col_begin : 0;
+    d->col_count = o ? o->col_count : 0;
+    if (d->col_begin < 0 || d->col_count < 0) {
+        set_error("negative column range");
+        return NEGF_E_INVALID_ARG;
+    }
     if (d->precision != NEGF_FP64 && d->precision != NEGF_MIXED) {
         set_error("unknown precision %d", d->precision);
         return NEGF_E_INVALID_ARG;
@@ -440,43 +445,8 @@ static negf_status read_opts(const negf_opts* o, Defaults* d) {
     return NEGF_OK;
 }
 
-// the multi-shift core stores every Krylov residual on the requested rows
-static constexpr int kChunkIters = 32;
-
-static negf_status ensure_vchunks(negf_op* op, int slots_needed, int w, int n_rows,
-                                  double2*** d_tab, hipStream_t s) {
-    const size_t chunk_bytes = (size_t)kChunkIters * w * n_rows * sizeof(double2);
-    // drop chunks of a different geometry
-    if (!op->vchunks.empty() && op->vchunks[0].bytes != chunk_bytes) {
-        HIPCHK(hipStreamSynchronize(s));
-        for (auto& b : op->vchunks)
-            if (b.ptr) (void)hipFree(b.ptr);
-        op->vchunks.clear();
-    }
-    const int need = (slots_needed + kChunkIters - 1) / kChunkIters;
-    bool grew = false;
-    while ((int)op->vchunks.size() < need) {
-        Buffer b;
-        CHK(dev_alloc(&b.ptr, chunk_bytes));
-        b.bytes = chunk_bytes;
-        op->vchunks.push_back(b);
-        grew = true;
-    }
-    const int cap = std::max<int>(need, (int)op->vchunks.size());
-    double2** tab = nullptr;
-    CHK(ws(op, WS_CHUNKTAB, (size_t)std::max(cap, 1024), &tab));
-    if (grew || need > 0) {
-        std::vector<double2*> h(op->vchunks.size());
-        for (size_t i = 0; i < h.size(); ++i) h[i] = (double2*)op->vchunks[i].ptr;
-        HIPCHK(hipMemcpyAsync(tab, h.data(), h.size() * sizeof(double2*), hipMemcpyHostToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
-    }
-    *d_tab = tab;
-    return NEGF_OK;
-}
-
 static negf_status make_state(negf_op* op, int w, int ng, int max_iter, double tol, bool hist,
-                              IterState* st) {
+                              IterState* st, int chunk = 0) {
     // one allocation carved into the state arrays
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
@@ -491,6 +461,8 @@ static negf_status make_state(negf_op* op, int w, int ng, int max_iter, double t
     const size_t o_pp = ng ? take((size_t)w * ng * sizeof(double2)) : 0;
     const size_t o_dl = ng ? take((size_t)w * ng * sizeof(double)) : 0;
     const size_t o_sc = ng ? take((size_t)w * ng * sizeof(int)) : 0;
+    const size_t o_sr = ng ? take((size_t)w * ng * sizeof(double)) : 0;
+    const size_t o_rc = (ng && chunk) ? take((size_t)w * chunk * 3 * ng * sizeof(double2)) : 0;
     unsigned char* base = nullptr;
     CHK(ws(op, WS_STATE, off, &base));
     st->w = w;
@@ -511,45 +483,108 @@ static negf_status make_state(negf_op* op, int w, int ng, int max_iter, double t
     st->pih_prev = ng ? (double2*)(base + o_pp) : nullptr;
     st->deltas = ng ? (double*)(base + o_dl) : nullptr;
     st->sconv = ng ? (int*)(base + o_sc) : nullptr;
+    st->sres = ng ? (double*)(base + o_sr) : nullptr;
+    st->rec = (ng && chunk) ? (double2*)(base + o_rc) : nullptr;
+    st->chunk = chunk;
     return NEGF_OK;
 }
 
+// HIP-event timing of the fused stencil launches (bench instrumentation):
+// pairs are recorded around each launch and summed at the drivers' sync points.
+struct MatvecTimer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;
+    int used = 0;
+    double seconds = 0.0;
+    int64_t launches = 0;
+    double bytes = 0.0;
+    static constexpr int kPool = 256;
+    negf_status init(bool enable) {
+        on = enable;
+        if (!on) return NEGF_OK;
+        ev.resize(2 * kPool);
+        for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+        return NEGF_OK;
+    }
+    // events for the next launch (null when off); flushes a full pool first
+    negf_status next(hipEvent_t* a, hipEvent_t* b) {
+        *a = *b = nullptr;
+        if (!on) return NEGF_OK;
+        if (used == kPool) CHK(flush());
+        *a = ev[2 * used];
+        *b = ev[2 * used + 1];
+        ++used;
+        return NEGF_OK;
+    }
+    negf_status flush() {
+        for (int i = 0; i < used; ++i) {
+            HIPCHK(hipEventSynchronize(ev[2 * i + 1]));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+            seconds += 1e-3 * ms;
+            ++launches;
+        }
+        used = 0;
+        return NEGF_OK;
+    }
+    ~MatvecTimer() {
+        for (auto& e : ev) (void)hipEventDestroy(e);
+    }
+};
+
 // Output of one multi-shift block.
 struct MSOut {
-    // transmission mode
-    double* h_tcol = nullptr;   // [w][ng] host
-    // column mode
-    double2* d_out = nullptr;   // device destination of X
+    double* h_tcol = nullptr;   // [w][ng] host (transmission mode)
+    double2* d_out = nullptr;   // device destination of X (column mode)
     int64_t out_col_stride = 0, out_shift_stride = 0;
-    // diagnostics (host, [w] and [w][ng])
-    int* h_iters = nullptr;
-    int* h_status = nullptr;
-    double* h_resid = nullptr;  // [w][ng]
+    int* h_iters = nullptr;     // [w]
+    int* h_status = nullptr;    // [w] column status
+    double* h_resid = nullptr;  // [w][ng] residual estimate per energy
+    int* h_shift_iters = nullptr; // [w][ng] iteration at which each energy converged (0: not)
 };
+
+// iterations per blocked shift update (and per ring half)
+static constexpr int kShiftChunk = 128;
 
 // One block of w columns through the multi-shift core (FP64).
 //   cols (host) unit right-hand sides, or d_rhs (device [w][N]) dense ones
-//   rows: contiguous [row0, row0+n_rows) when d_rows == null
+//   rows kept per energy: contiguous [row0, row0+n_rows) when d_rows == null
 static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, const int* cols,
                                         const double2* d_rhs, const double* energies, int ng,
                                         const int* d_rows, int64_t row0, int n_rows,
                                         const double* d_row_w, const double* h_col_w,
-                                        const MSOut& out, int64_t* total_iters, hipStream_t s) {
+                                        const MSOut& out, int64_t* total_iters, hipStream_t s,
+                                        MatvecTimer* tm) {
     const int64_t N = op->N;
     const int nblk = part_blocks(N);
-    double2 *r, *p, *q, *part, *kbc;
+    const int nblk_f = fused_partials(op, w);
+    const int ch = kShiftChunk, ring_len = 2 * kShiftChunk;
+    double2 *r, *p, *p2, *q, *part, *kbc, *ring, *X, *P, *coef, *part_f;
     double *part_nn, *shift;
     int* d_cols;
     CHK(ws(op, WS_R, (size_t)w * N, &r));
     CHK(ws(op, WS_P, (size_t)w * N, &p));
     CHK(ws(op, WS_Q, (size_t)w * N, &q));
+    CHK(ws(op, WS_X, (size_t)w * N, &p2));
     CHK(ws(op, WS_PART, (size_t)w * nblk, &part));
     CHK(ws(op, WS_PART2, (size_t)w * nblk, &part_nn));
+    CHK(ws(op, WS_PART3, (size_t)w * nblk_f, &part_f));
     CHK(ws(op, WS_KBC, (size_t)w * std::max(1, op->kb.n_proj), &kbc));
     CHK(ws(op, WS_SHIFT, (size_t)w, &shift));
     CHK(ws(op, WS_COLJ, (size_t)w, &d_cols));
+    CHK(ws(op, WS_RING, (size_t)ring_len * w * n_rows, &ring));
+    CHK(ws(op, WS_XS, (size_t)w * ng * n_rows, &X));
+    CHK(ws(op, WS_PS, (size_t)w * ng * n_rows, &P));
+    // coefficients: CX, CP [w][ch][ng]; xi_a [w][ng][2]; carry [w][ng]; active [w][ng]
+    const size_t n_cxp = (size_t)w * ch * ng;
+    CHK(ws(op, WS_COEF, 2 * n_cxp + 3 * (size_t)w * ng + ((size_t)w * ng + 1) / 2, &coef));
+    double2* cx = coef;
+    double2* cp = coef + n_cxp;
+    double2* xi_a = coef + 2 * n_cxp;
+    double2* carry = xi_a + 2 * (size_t)w * ng;
+    int* active = (int*)(carry + (size_t)w * ng);
     IterState st;
-    CHK(make_state(op, w, ng, d.max_iter, d.tol, true, &st));
+    CHK(make_state(op, w, ng, d.max_iter, d.tol, true, &st, ch));
 
     // seed: the highest energy of the group (usually the slowest system)
     double e_seed = energies[0];
@@ -565,70 +600,72 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, c
     } else {
         HIPCHK(hipMemcpyAsync(r, d_rhs, (size_t)w * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
     }
+    HIPCHK(hipMemsetAsync(X, 0, (size_t)w * ng * n_rows * sizeof(double2), s));
+    HIPCHK(hipMemsetAsync(P, 0, (size_t)w * ng * n_rows * sizeof(double2), s));
+    HIPCHK(hipMemsetAsync(carry, 0, (size_t)w * ng * sizeof(double2), s));
     launch_norms<double>(r, N, w, nullptr, part, part_nn, s);
     launch_reduce_init(part, part_nn, nblk, st, nullptr, s);
-    double2** tab = nullptr;
-    CHK(ensure_vchunks(op, kChunkIters, w, n_rows, &tab, s));
-    launch_store_rows<double>(r, N, w, d_rows, row0, n_rows, tab, kChunkIters, st, 0, s);
+    launch_store_rows<double>(r, N, w, d_rows, row0, n_rows, ring, ring_len, st, 0, s);
     HIPCHK(hipGetLastError());
 
     std::vector<int> h_done(w), h_k(w);
-    int k_host = 0;
-    const int chunk = 16;
+    int k0 = 0;
     while (true) {
-        const int steps = std::min(chunk, d.max_iter - k_host);
-        CHK(ensure_vchunks(op, k_host + steps + 2, w, n_rows, &tab, s));
+        const int steps = std::min(ch, d.max_iter - k0);
         for (int it = 0; it < steps; ++it) {
-            launch_p_update<double>(r, p, st, N, s);
-            launch_apply<double>(op, p, q, w, shift, st.done, kbc, s);
-            launch_dot_pq<double>(p, q, part, st, N, s);
-            launch_reduce_alpha(part, nblk, st, s);
+            // p ping-pongs so that halo reads of the fused kernel see p_{k-1}
+            const int k = k0 + it;
+            double2* pin = (k & 1) ? p2 : p;
+            double2* pout = (k & 1) ? p : p2;
+            hipEvent_t e0, e1;
+            CHK(tm->next(&e0, &e1));
+            launch_cocg_apply<double>(op, r, pin, pout, q, w, shift, st.done, st.k, st.beta, part_f,
+                                      kbc, s, e0, e1);
+            launch_reduce_alpha(part_f, nblk_f, st, s, op->kb.n_proj ? kbc : nullptr, op->kb.e,
+                                op->kb.n_proj);
             launch_r_update<double>(r, q, nullptr, nullptr, part, part_nn, st, N, s);
-            launch_store_rows<double>(r, N, w, d_rows, row0, n_rows, tab, kChunkIters, st, 1, s);
+            launch_store_rows<double>(r, N, w, d_rows, row0, n_rows, ring, ring_len, st, 1, s);
             launch_reduce_beta_multishift(part, part_nn, nblk, st, s);
         }
+        // fold the chunk's iterations into X and P of every energy
+        launch_chunk_coef(st, k0, cx, cp, xi_a, carry, active, s);
+        launch_gemm_xp(ring, ring_len, w, n_rows, k0, st, cx, cp, xi_a, active, X, P, s);
         HIPCHK(hipGetLastError());
-        k_host += steps;
+        k0 += steps;
         HIPCHK(hipMemcpyAsync(h_done.data(), st.done, w * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        CHK(tm->flush());
         bool all = true;
         for (int c = 0; c < w; ++c) all = all && h_done[c] != 0;
-        if (all || k_host >= d.max_iter) break;
+        if (all || k0 >= d.max_iter) break;
     }
-    // columns still running at max_iter
     HIPCHK(hipMemcpyAsync(h_k.data(), st.k, w * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    int m_max = 1;
+    if (tm->on) {
+        // per column-iteration: r, p_{k-1} read, p_k, q written; V once per launch
+        int64_t col_iters = 0;
+        for (int c = 0; c < w; ++c) col_iters += h_k[c];
+        tm->bytes += 4.0 * sizeof(double2) * (double)N * (double)col_iters + 8.0 * N * k0;
+    }
     for (int c = 0; c < w; ++c) {
-        m_max = std::max(m_max, h_k[c]);
         *total_iters += h_k[c];
         if (out.h_iters) out.h_iters[c] = h_k[c];
         if (out.h_status) out.h_status[c] = h_done[c] ? h_done[c] - 1 : NEGF_ITEM_MAX_ITER;
     }
-    // coefficients of the stored basis for every energy
-    double2 *gamma, *tri;
-    double* resid;
-    CHK(ws(op, WS_GAMMA, (size_t)w * m_max * ng, &gamma));
-    CHK(ws(op, WS_TRI, (size_t)w * m_max * 4 * ng, &tri));
-    CHK(ws(op, WS_MISC, (size_t)w * ng, &resid));
-    launch_tridiag_solve(st, st.k, gamma, m_max, tri, resid, s);
     if (out.h_tcol) {
-        const int n_tiles = (n_rows + 63) / 64;
-        double *tpart, *tcol, *col_w;
-        CHK(ws(op, WS_TPART, (size_t)w * n_tiles * ng, &tpart));
+        double *tcol, *col_w;
         CHK(ws(op, WS_TCOL, (size_t)w * ng + w, &tcol));
         col_w = tcol + (size_t)w * ng;
         HIPCHK(hipMemcpyAsync(col_w, h_col_w, w * sizeof(double), hipMemcpyHostToDevice, s));
-        launch_gemm_reduce(tab, kChunkIters, w, n_rows, st.k, gamma, m_max, ng, d_row_w, tpart, s);
-        launch_sum_tpart(tpart, n_tiles, w, ng, col_w, tcol, s);
+        launch_t_from_x(X, n_rows, w, ng, d_row_w, col_w, tcol, s);
         HIPCHK(hipMemcpyAsync(out.h_tcol, tcol, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
     }
-    if (out.d_out) {
-        launch_gemm_store(tab, kChunkIters, w, n_rows, st.k, gamma, m_max, ng, out.d_out,
-                          out.out_col_stride, out.out_shift_stride, s);
-    }
+    if (out.d_out)
+        launch_copy_out(X, n_rows, w, ng, out.d_out, out.out_col_stride, out.out_shift_stride, s);
     if (out.h_resid)
-        HIPCHK(hipMemcpyAsync(out.h_resid, resid, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(out.h_resid, st.sres, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (out.h_shift_iters)
+        HIPCHK(hipMemcpyAsync(out.h_shift_iters, st.sconv, (size_t)w * ng * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     return NEGF_OK;
@@ -657,18 +694,22 @@ struct PEOut {
 template <typename R>
 static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, const int* cols,
                                         const double2* d_rhs, const double* item_e,
-                                        const PEOut& out, int64_t* total_iters, hipStream_t s) {
+                                        const PEOut& out, int64_t* total_iters, hipStream_t s,
+                                        MatvecTimer* tm) {
     const int64_t N = op->N;
     const int nblk = part_blocks(N);
-    cplx_t<R> *r, *p, *q, *dsol;
-    double2 *b64, *x64, *r64, *q64, *part, *kbc;
+    const int nblk_f = fused_partials(op, w);
+    cplx_t<R> *r, *p, *p2, *q, *dsol;
+    double2 *b64, *x64, *r64, *q64, *part, *kbc, *part_f;
     double *part_nn, *shift, *misc;
     int* d_cols;
     CHK(ws(op, WS_R, (size_t)w * N, &r));
     CHK(ws(op, WS_P, (size_t)w * N, &p));
+    CHK(ws(op, WS_RING, (size_t)w * N, &p2));
     CHK(ws(op, WS_Q, (size_t)w * N, &q));
     CHK(ws(op, WS_X, (size_t)w * N, &dsol));
     CHK(ws(op, WS_B, (size_t)w * N, &b64));
+    CHK(ws(op, WS_PART3, (size_t)w * nblk_f, &part_f));
     CHK(ws(op, WS_X64, (size_t)w * N, &x64));
     CHK(ws(op, WS_R64, (size_t)w * N, &r64));
     CHK(ws(op, WS_Q64, (size_t)w * N, &q64));
@@ -725,25 +766,37 @@ static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, c
         while (true) {
             const int steps = std::min(16, d.max_iter - k_host);
             for (int it = 0; it < steps; ++it) {
-                launch_p_update<R>(r, p, st, N, s);
-                launch_apply<R>(op, p, q, w, shift, st.done, kbc, s);
-                launch_dot_pq<R>(p, q, part, st, N, s);
-                launch_reduce_alpha(part, nblk, st, s);
-                launch_r_update<R>(r, q, p, dsol, part, part_nn, st, N, s);
+                const int k = k_host + it;
+                cplx_t<R>* pin = (k & 1) ? p2 : p;
+                cplx_t<R>* pout = (k & 1) ? p : p2;
+                hipEvent_t e0, e1;
+                CHK(tm->next(&e0, &e1));
+                launch_cocg_apply<R>(op, r, pin, pout, q, w, shift, st.done, st.k, st.beta, part_f,
+                                     kbc, s, e0, e1);
+                launch_reduce_alpha(part_f, nblk_f, st, s, op->kb.n_proj ? kbc : nullptr, op->kb.e,
+                                    op->kb.n_proj);
+                launch_r_update<R>(r, q, pout, dsol, part, part_nn, st, N, s);
                 launch_reduce_beta_single(part, part_nn, nblk, st, inner_tol, s);
             }
             HIPCHK(hipGetLastError());
             k_host += steps;
             HIPCHK(hipMemcpyAsync(h_done.data(), st.done, w * sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
+            CHK(tm->flush());
             bool alld = true;
             for (int c = 0; c < w; ++c) alld = alld && h_done[c];
             if (alld || k_host >= d.max_iter) break;
         }
         HIPCHK(hipMemcpyAsync(h_k.data(), st.k, w * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        int64_t col_iters = 0;
         for (int c = 0; c < w; ++c)
-            if (!h_odone[c]) iters[c] += h_k[c];
+            if (!h_odone[c]) {
+                iters[c] += h_k[c];
+                col_iters += h_k[c];
+            }
+        if (tm->on)
+            tm->bytes += 4.0 * sizeof(cplx_t<R>) * (double)N * (double)col_iters + 8.0 * N * k_host;
         launch_accumulate<R>(x64, dsol, N, w, odone, nu, s);
     }
     for (int c = 0; c < w; ++c) {
@@ -761,10 +814,10 @@ static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, c
 
 static negf_status run_per_energy(negf_op* op, const Defaults& d, int w, const int* cols,
                                   const double2* d_rhs, const double* item_e, const PEOut& out,
-                                  int64_t* total_iters, hipStream_t s) {
+                                  int64_t* total_iters, hipStream_t s, MatvecTimer* tm) {
     if (d.precision == NEGF_MIXED)
-        return run_per_energy_block<float>(op, d, w, cols, d_rhs, item_e, out, total_iters, s);
-    return run_per_energy_block<double>(op, d, w, cols, d_rhs, item_e, out, total_iters, s);
+        return run_per_energy_block<float>(op, d, w, cols, d_rhs, item_e, out, total_iters, s, tm);
+    return run_per_energy_block<double>(op, d, w, cols, d_rhs, item_e, out, total_iters, s, tm);
 }
 
 // ---------------------------------------------------------------------------
@@ -777,6 +830,20 @@ struct Sides {
     int n_rows = 0;
     std::vector<double> roww;
 };
+
+static negf_status restrict_sides(const Defaults& d, Sides* sd) {
+    const int n = (int)sd->cols.size();
+    if (d.col_begin == 0 && d.col_count == 0) return NEGF_OK;
+    const int cnt = d.col_count ? d.col_count : n - d.col_begin;
+    if (d.col_begin >= n || cnt < 1 || d.col_begin + cnt > n) {
+        set_error("column range [%d, %d) outside the %d source columns", d.col_begin,
+                  d.col_begin + cnt, n);
+        return NEGF_E_INVALID_ARG;
+    }
+    sd->cols = std::vector<int>(sd->cols.begin() + d.col_begin, sd->cols.begin() + d.col_begin + cnt);
+    sd->colw = std::vector<double>(sd->colw.begin() + d.col_begin, sd->colw.begin() + d.col_begin + cnt);
+    return NEGF_OK;
+}
 
 static void make_sides(const negf_op* op, int direction, Sides* sd) {
     const int64_t plane = (int64_t)op->nx * op->ny;
@@ -846,8 +913,11 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
     HIPCHK(hipSetDevice(op->device));
     hipStream_t s = pick_stream(op, opts);
     const auto t0 = std::chrono::steady_clock::now();
+    MatvecTimer tm;
+    CHK(tm.init(diag && diag->time_matvec));
     Sides sd;
     make_sides(op, d.direction, &sd);
+    CHK(restrict_sides(d, &sd));
     const int n_cols = (int)sd.cols.size();
     double* d_roww = nullptr;
     CHK(ws(op, WS_ROWW, (size_t)sd.n_rows, &d_roww));
@@ -861,7 +931,7 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
         const int ng_max = d.shift_group ? std::min(d.shift_group, n_e) : n_e;
         const int wmax = d.block_width ? d.block_width : 64;
         std::vector<double> blk_t, blk_r;
-        std::vector<int> blk_it, blk_st;
+        std::vector<int> blk_it, blk_st, blk_si;
         for (int g0 = 0; g0 < n_e; g0 += ng_max) {
             const int ng = std::min(ng_max, n_e - g0);
             for (int c0 = 0; c0 < n_cols; c0 += wmax) {
@@ -870,20 +940,23 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
                 blk_r.assign((size_t)w * ng, 0.0);
                 blk_it.assign(w, 0);
                 blk_st.assign(w, 0);
+                blk_si.assign((size_t)w * ng, 0);
                 MSOut mo;
                 mo.h_tcol = blk_t.data();
                 mo.h_iters = blk_it.data();
                 mo.h_status = blk_st.data();
                 mo.h_resid = blk_r.data();
+                mo.h_shift_iters = blk_si.data();
                 CHK(run_multishift_block(op, d, w, sd.cols.data() + c0, nullptr, energies + g0, ng,
                                          nullptr, sd.row0, sd.n_rows, d_roww, sd.colw.data() + c0,
-                                         mo, &total_iters, s));
+                                         mo, &total_iters, s, &tm));
                 for (int c = 0; c < w; ++c)
                     for (int g = 0; g < ng; ++g) {
                         const size_t o = (size_t)(g0 + g) * n_cols + c0 + c;
                         tcol[o] = blk_t[(size_t)c * ng + g];
                         resid[o] = blk_r[(size_t)c * ng + g];
-                        iters[o] = blk_it[c];
+                        // iterations this energy needed (the column's count if it never froze)
+                        iters[o] = blk_si[(size_t)c * ng + g] ? blk_si[(size_t)c * ng + g] : blk_it[c];
                         // a column that hit max_iter can still have converged
                         // energies; judge each by its own residual estimate
                         status[o] = (blk_st[c] == NEGF_ITEM_BREAKDOWN) ? NEGF_ITEM_BREAKDOWN
@@ -917,7 +990,7 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
             po.h_iters = b_it.data();
             po.h_status = b_st.data();
             po.h_resid = b_res.data();
-            CHK(run_per_energy(op, d, w, icol.data(), nullptr, ie.data(), po, &total_iters, s));
+            CHK(run_per_energy(op, d, w, icol.data(), nullptr, ie.data(), po, &total_iters, s, &tm));
             double2* x64 = (double2*)op->bufs[WS_X64].ptr;
             HIPCHK(hipMemcpyAsync(d_colw, colw.data(), w * sizeof(double), hipMemcpyHostToDevice, s));
             launch_weighted_norm(x64, op->N, w, sd.row0, sd.n_rows, d_roww, d_colw, d_t, s);
@@ -953,6 +1026,9 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
         diag->total_iters = total_iters;
         diag->n_not_converged = n_bad + n_break;
         diag->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        diag->matvec_seconds = tm.seconds;
+        diag->matvec_launches = tm.launches;
+        diag->matvec_bytes = tm.bytes;
     }
     return final_status(n_bad, n_break);
 }
@@ -1006,6 +1082,7 @@ static negf_status solve_columns_impl(negf_op* op, const negf_opts* opts, int32_
     }
     HIPCHK(hipSetDevice(op->device));
     hipStream_t s = pick_stream(op, opts);
+    MatvecTimer tm;
     const size_t out_elems = (size_t)n_e * n_rhs * n_rows;
     const bool out_dev = is_device_ptr(out);
     double2* d_out = nullptr;
@@ -1051,7 +1128,7 @@ static negf_status solve_columns_impl(negf_op* op, const negf_opts* opts, int32_
                 CHK(run_multishift_block(op, d, w, rhs_idx ? rhs_idx + c0 : nullptr,
                                          d_rhs_all ? d_rhs_all + (size_t)c0 * N : nullptr,
                                          energies + g0, ng, d_rows, 0, n_rows, nullptr, nullptr,
-                                         mo, &total_iters, s));
+                                         mo, &total_iters, s, &tm));
                 for (int c = 0; c < w; ++c)
                     for (int g = 0; g < ng; ++g)
                         status[(size_t)(g0 + g) * n_rhs + c0 + c] =
@@ -1086,7 +1163,7 @@ static negf_status solve_columns_impl(negf_op* op, const negf_opts* opts, int32_
             PEOut po;
             po.h_status = b_st2.data();
             CHK(run_per_energy(op, d, w, rhs_idx ? icol.data() : nullptr, d_rhs_blk, ie.data(), po,
-                               &total_iters, s));
+                               &total_iters, s, &tm));
             HIPCHK(hipMemcpyAsync(d_dst, dst.data(), w * sizeof(int64_t), hipMemcpyHostToDevice, s));
             launch_gather((double2*)op->bufs[WS_X64].ptr, N, w, d_rows, n_rows, d_dst, d_out, s);
             HIPCHK(hipStreamSynchronize(s));
@@ -1134,10 +1211,12 @@ static negf_status grad_impl(negf_op* op, const negf_opts* opts, int32_t n_e,
     }
     HIPCHK(hipSetDevice(op->device));
     hipStream_t s = pick_stream(op, opts);
+    MatvecTimer tm;
     const int64_t N = op->N;
     const int64_t plane = (int64_t)op->nx * op->ny;
     Sides sd;
     make_sides(op, NEGF_DIR_RL, &sd);
+    CHK(restrict_sides(d, &sd));
     const int n_cols = (int)sd.cols.size();
     const int wmax = d.block_width ? d.block_width : 32;
     double *d_field, *d_colw, *d_roww, *d_t;
@@ -1167,7 +1246,7 @@ static negf_status grad_impl(negf_op* op, const negf_opts* opts, int32_t n_e,
             Defaults d64 = d;
             d64.precision = NEGF_FP64;
             // forward columns g_j
-            CHK(run_per_energy(op, d64, w, sd.cols.data() + c0, nullptr, ie.data(), po, &total_iters, s));
+            CHK(run_per_energy(op, d64, w, sd.cols.data() + c0, nullptr, ie.data(), po, &total_iters, s, &tm));
             double2* x64 = (double2*)op->bufs[WS_X64].ptr;
             HIPCHK(hipMemcpyAsync(d_g, x64, (size_t)w * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
             HIPCHK(hipMemcpyAsync(d_colw, colw.data(), w * sizeof(double), hipMemcpyHostToDevice, s));
@@ -1176,7 +1255,7 @@ static negf_status grad_impl(negf_op* op, const negf_opts* opts, int32_t n_e,
             // adjoint right-hand sides W_L o conj(g_j) and solves with the same operator
             launch_adjoint_rhs(d_g, N, plane, w, op->d_wl, d_rhs, s);
             po.h_status = st2.data();
-            CHK(run_per_energy(op, d64, w, nullptr, d_rhs, ie.data(), po, &total_iters, s));
+            CHK(run_per_energy(op, d64, w, nullptr, d_rhs, ie.data(), po, &total_iters, s, &tm));
             x64 = (double2*)op->bufs[WS_X64].ptr;
             // 8 Re sum_j W_R,j g_j lambda_j = 2 Re sum_j (4 W_R,j) g_j lambda_j
             launch_field(d_g, x64, N, w, d_colw, 2.0 * weights[e], d_field, s);

@@ -81,7 +81,6 @@ struct negf_op {
     DeviceKB kb;
     hipStream_t own_stream = nullptr;
     std::vector<Buffer> bufs;    // workspace, indexed by WorkSlot
-    std::vector<Buffer> vchunks; // stored Krylov vectors (multi-shift)
 };
 
 // status plumbing (thread-local message)
@@ -98,7 +97,7 @@ enum WorkSlot {
     WS_R = 0, WS_P, WS_Q, WS_X, WS_B, WS_R64, WS_X64, WS_Q64,
     WS_PART, WS_PART2, WS_PART3, WS_KBC, WS_SHIFT, WS_COLJ,
     WS_STATE, WS_HIST, WS_PI, WS_GAMMA, WS_TRI, WS_TPART, WS_TCOL, WS_ROWS,
-    WS_ROWW, WS_CHUNKTAB, WS_MISC, WS_COUNT
+    WS_ROWW, WS_RING, WS_XS, WS_PS, WS_COEF, WS_MISC, WS_COUNT
 };
 negf_status ws_get(negf_op* op, int slot, size_t bytes, void** out);
 
@@ -129,7 +128,13 @@ struct IterState {
     double2* pih = nullptr;    // [w][ng] scaled pi_k
     double2* pih_prev = nullptr; // [w][ng]
     double* deltas = nullptr;  // [w][ng] real shifts E_sigma - E_seed (per column)
-    int* sconv = nullptr;      // [w][ng] shift converged (sticky; its recurrence is frozen)
+    int* sconv = nullptr;      // [w][ng] 0, or the iteration at which the shift converged
+                               // (sticky: its recurrence is frozen from then on)
+    double* sres = nullptr;    // [w][ng] residual estimate ||r_sigma|| / ||b|| (at freeze)
+    // per-iteration shifted COCG scalars for the blocked accumulation:
+    // rec[((c*chunk + k%chunk)*3 + t)*ng + g], t = 0: 1/pi_k, 1: alpha^sigma_k, 2: beta^sigma_k
+    double2* rec = nullptr;
+    int chunk = 0;
     int* running = nullptr;    // [1] count of running columns after a step
     double tol = 1e-10;
 };
@@ -140,7 +145,17 @@ void launch_p_update(const cplx_t<R>* r, cplx_t<R>* p, const IterState& st, int6
 template <typename R>
 void launch_dot_pq(const cplx_t<R>* p, const cplx_t<R>* q, double2* part, const IterState& st,
                    int64_t N, hipStream_t s);
-void launch_reduce_alpha(const double2* part, int nblk, IterState st, hipStream_t s);
+void launch_reduce_alpha(const double2* part, int nblk, IterState st, hipStream_t s,
+                         const double2* kbc = nullptr, const double* e_kb = nullptr,
+                         int n_proj = 0);
+// fused p-update + operator apply + p^T q partials (stencil.hip); the projector
+// gather/scatter follow it.  ev0/ev1 (nullable) bracket the stencil kernel.
+template <typename R>
+void launch_cocg_apply(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin,
+                       cplx_t<R>* pout, cplx_t<R>* q, int w, const double* shift, const int* skip,
+                       const int* kit, const double2* beta, double2* part, double2* d_kbc,
+                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+int fused_partials(const negf_op* op, int w);
 template <typename R>
 void launch_r_update(cplx_t<R>* r, const cplx_t<R>* q, cplx_t<R>* p_or_null, cplx_t<R>* x_or_null,
                      double2* part_rr, double* part_nn, const IterState& st, int64_t N,
@@ -151,16 +166,16 @@ void launch_reduce_beta_single(const double2* part_rr, const double* part_nn, in
                                IterState st, double inner_tol, hipStream_t s);
 template <typename R>
 void launch_store_rows(const cplx_t<R>* r, int64_t N, int w, const int* rows, int64_t row0,
-                       int n_rows, double2* const* chunk_tab, int chunk_iters,
-                       const IterState& st, int slot_offset, hipStream_t s);
-void launch_tridiag_solve(IterState st, const int* m_col, double2* gamma, int m_max,
-                          double2* tri, double* resid_out, hipStream_t s);
-void launch_gemm_reduce(double2* const* chunk_tab, int chunk_iters, int w, int n_rows,
-                        const int* m_col, const double2* gamma, int m_max, int ng,
-                        const double* row_w, double* tpart, hipStream_t s);
-void launch_gemm_store(double2* const* chunk_tab, int chunk_iters, int w, int n_rows,
-                       const int* m_col, const double2* gamma, int m_max, int ng,
-                       double2* out, int64_t out_col_stride, int64_t out_shift_stride,
-                       hipStream_t s);
-void launch_sum_tpart(const double* tpart, int n_tiles, int w, int ng, const double* col_w,
-                      double* tcol, hipStream_t s);
+                       int n_rows, double2* ring, int ring_len, const IterState& st,
+                       int slot_offset, hipStream_t s);
+// blocked multi-shift accumulation (shift.hip)
+void launch_chunk_coef(const IterState& st, int k0, double2* cx, double2* cp, double2* xi_a,
+                       double2* carry, int* active, hipStream_t s);
+void launch_gemm_xp(const double2* ring, int ring_len, int w, int n_rows, int k0,
+                    const IterState& st, const double2* cx, const double2* cp,
+                    const double2* xi_a, const int* active, double2* X, double2* P,
+                    hipStream_t s);
+void launch_t_from_x(const double2* X, int n_rows, int w, int ng, const double* row_w,
+                     const double* col_w, double* t, hipStream_t s);
+void launch_copy_out(const double2* X, int n_rows, int w, int ng, double2* out, int64_t col_stride,
+                     int64_t shift_stride, hipStream_t s);

@@ -14,6 +14,8 @@
 // HBM sees each input plane once per tile (halo rows are re-read through L2
 // by the neighbouring tile, which runs at the same z on the same XCD because
 // the tiles of one column are issued consecutively).
+#include <algorithm>
+
 #include "negf_internal.h"
 
 namespace {
@@ -295,3 +297,303 @@ template void launch_apply<double>(const negf_op*, const double2*, double2*, int
                                    const int*, double2*, hipStream_t);
 template void launch_apply<float>(const negf_op*, const float2*, float2*, int, const double*,
                                   const int*, double2*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Fused COCG step on the operator (the hot loop of both solver cores):
+//     p_k = r_k + beta_{k-1} p_{k-1}   (p_k = r_k at k = 0)
+//     q_k = (A(E_c) - projector term) p_k,   partial sums of p_k^T q_k
+// in one pass: HBM sees r and p_{k-1} once (read) and p_k, q_k once (write).
+// Without FUSED the same kernel is the plain apply y = A x (x passed as pin).
+//
+// Work-group: NT threads own a tile of TY full x-rows (TY = NT/nx rows,
+// or all ny rows when they fit; then no y-halo exists) of one column and a
+// z-chunk.  Each thread owns one (x, y) column of the tile:
+//   * register queue of the 2R+1 values of p along z,
+//   * the next lead plane's r and p_{k-1} are prefetched one plane ahead,
+//   * the centre plane (plus y-halo rows, recomputed from r and p_{k-1})
+//     is staged in a double-buffered LDS tile: one barrier per plane.
+// p_k is written by the owner of each plane only (no write races), and the
+// p buffers ping-pong between iterations so halo reads see p_{k-1}.
+// ---------------------------------------------------------------------------
+template <int RAD, typename R, int NT, bool FUSED>
+__global__ __launch_bounds__(NT) void k_cocg_apply(
+    const cplx_t<R>* __restrict__ r, const cplx_t<R>* __restrict__ pin, cplx_t<R>* __restrict__ pout,
+    cplx_t<R>* __restrict__ y, int nx, int ny, int nz, int ty, int n_ytiles, int zchunk,
+    Coef<R> cf, double a0, const double* __restrict__ v, const double* __restrict__ wz,
+    const double* __restrict__ shift, const int* __restrict__ skip, const int* __restrict__ kit,
+    const double2* __restrict__ beta, double2* __restrict__ part) {
+    extern __shared__ unsigned char smem_raw[];
+    const int c = blockIdx.y;
+    if (skip && skip[c]) return;
+    const int bid = blockIdx.x;
+    const int ytile = bid % n_ytiles;
+    const int z0 = (bid / n_ytiles) * zchunk;
+    const int z1 = min(nz, z0 + zchunk);
+    const int y0 = ytile * ty;
+    const int rows = min(ty, ny - y0);
+    const int pitch = nx + 2 * RAD;
+    const int lrows = ty + 2 * RAD;
+    cplx_t<R>* tile0 = reinterpret_cast<cplx_t<R>*>(smem_raw);
+    cplx_t<R>* tile1 = tile0 + pitch * lrows;
+    const int64_t plane = (int64_t)nx * ny;
+    const int64_t N = plane * nz;
+    const int64_t co = (int64_t)c * N;
+    const int tid = threadIdx.x;
+    const int lx = tid % nx;
+    const int ly = tid / nx;  // < rows for the threads that own a point
+    const bool own = ly < rows;
+    const int64_t col_off = (int64_t)(y0 + (own ? ly : 0)) * nx + lx;
+    const double e_c = shift[c] + a0;
+    const bool first = FUSED ? (kit[c] == 0) : true;
+    const double2 bb = FUSED ? beta[c] : make_double2(0.0, 0.0);
+    const R bx = (R)bb.x, byy = (R)bb.y;
+    const bool has_halo = rows < ny;
+
+    // p at (plane zz, tile-relative row yy, x) from r and p_{k-1} (FUSED) or x (plain)
+    auto p_at = [&](int64_t gi) -> cplx_t<R> {
+        if (!FUSED) return pin[co + gi];
+        const cplx_t<R> rv = r[co + gi];
+        if (first) return rv;
+        const cplx_t<R> pv = pin[co + gi];
+        cplx_t<R> o;
+        o.x = rv.x + bx * pv.x - byy * pv.y;
+        o.y = rv.y + bx * pv.y + byy * pv.x;
+        return o;
+    };
+
+    // zero both LDS tiles (x padding and out-of-grid rows stay zero)
+    for (int k = tid; k < 2 * pitch * lrows; k += NT) {
+        tile0[k].x = 0;
+        tile0[k].y = 0;
+    }
+    cplx_t<R> q[2 * RAD + 1];
+#pragma unroll
+    for (int d = 0; d < 2 * RAD; ++d) {
+        const int zz = z0 + d - RAD;
+        cplx_t<R> val;
+        val.x = 0;
+        val.y = 0;
+        if (own && zz >= 0 && zz < nz) val = p_at((int64_t)zz * plane + col_off);
+        q[d] = val;
+    }
+    // prefetch of the lead plane z0 + RAD
+    cplx_t<R> nr, np;
+    nr.x = nr.y = np.x = np.y = 0;
+    {
+        const int zl = z0 + RAD;
+        if (own && zl < nz) {
+            const int64_t gi = co + (int64_t)zl * plane + col_off;
+            if (FUSED) {
+                nr = r[gi];
+                if (!first) np = pin[gi];
+            } else {
+                np = pin[gi];
+            }
+        }
+    }
+    double dot_x = 0.0, dot_y = 0.0;
+    __syncthreads();
+    for (int z = z0; z < z1; ++z) {
+        cplx_t<R>* tile = (z & 1) ? tile1 : tile0;
+        // lead plane z + RAD from the prefetched values
+        {
+            cplx_t<R> lead;
+            if (!FUSED) {
+                lead = np;
+            } else if (first) {
+                lead = nr;
+            } else {
+                lead.x = nr.x + bx * np.x - byy * np.y;
+                lead.y = nr.y + bx * np.y + byy * np.x;
+            }
+            q[2 * RAD] = lead;
+        }
+        // prefetch plane z + RAD + 1
+        {
+            const int zl = z + RAD + 1;
+            nr.x = nr.y = np.x = np.y = 0;
+            if (own && zl < nz && z + 1 < z1) {
+                const int64_t gi = co + (int64_t)zl * plane + col_off;
+                if (FUSED) {
+                    nr = r[gi];
+                    if (!first) np = pin[gi];
+                } else {
+                    np = pin[gi];
+                }
+            }
+        }
+        // stage the centre plane
+        if (own) {
+            tile[(ly + RAD) * pitch + RAD + lx] = q[RAD];
+            if (FUSED) pout[co + (int64_t)z * plane + col_off] = q[RAD];
+        }
+        if (has_halo) {
+            for (int k = tid; k < 2 * RAD * nx; k += NT) {
+                const int hr = k / nx, hx = k % nx;
+                const int yy = hr < RAD ? (hr - RAD) : (rows + hr - RAD);
+                const int gy = y0 + yy;
+                cplx_t<R> val;
+                val.x = 0;
+                val.y = 0;
+                if (gy >= 0 && gy < ny) val = p_at((int64_t)z * plane + (int64_t)gy * nx + hx);
+                tile[(yy + RAD) * pitch + RAD + hx] = val;
+            }
+        }
+        __syncthreads();
+        if (own) {
+            const int64_t gi = (int64_t)z * plane + col_off;
+            const cplx_t<R> xi = q[RAD];
+            const R dr = (R)(e_c - v[gi]);
+            const R di = (R)wz[z];
+            R ax = dr * xi.x - di * xi.y;
+            R ay = dr * xi.y + di * xi.x;
+            const cplx_t<R>* row = tile + (ly + RAD) * pitch + RAD + lx;
+#pragma unroll
+            for (int m = 1; m <= RAD; ++m) {
+                const cplx_t<R> a0v = row[-m], a1v = row[m];
+                const cplx_t<R> b0v = row[-m * pitch], b1v = row[m * pitch];
+                const cplx_t<R> c0v = q[RAD - m], c1v = q[RAD + m];
+                ax += cf.a[m] * ((a0v.x + a1v.x) + (b0v.x + b1v.x) + (c0v.x + c1v.x));
+                ay += cf.a[m] * ((a0v.y + a1v.y) + (b0v.y + b1v.y) + (c0v.y + c1v.y));
+            }
+            cplx_t<R> o;
+            o.x = ax;
+            o.y = ay;
+            y[co + gi] = o;
+            if (FUSED) {
+                dot_x += (double)xi.x * ax - (double)xi.y * ay;
+                dot_y += (double)xi.x * ay + (double)xi.y * ax;
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 2 * RAD; ++d) q[d] = q[d + 1];
+    }
+    if (FUSED) {
+        // block reduction of p^T q (waves, then LDS; tile0 is free to reuse)
+        __syncthreads();
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            dot_x += __shfl_xor(dot_x, o, 64);
+            dot_y += __shfl_xor(dot_y, o, 64);
+        }
+        double* red = reinterpret_cast<double*>(smem_raw);
+        const int wave = tid / 64;
+        if (tid % 64 == 0) {
+            red[2 * wave] = dot_x;
+            red[2 * wave + 1] = dot_y;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double sx = 0.0, sy = 0.0;
+            for (int wv = 0; wv < NT / 64; ++wv) {
+                sx += red[2 * wv];
+                sy += red[2 * wv + 1];
+            }
+            part[(int64_t)c * gridDim.x + bid] = make_double2(sx, sy);
+        }
+    }
+}
+
+namespace {
+
+struct FusedGeom {
+    int nt, ty, n_ytiles, zchunk, n_z;
+    size_t lds;
+};
+
+template <int RAD, typename R>
+FusedGeom fused_geom(const negf_op* op, int w) {
+    FusedGeom g;
+    const int nx = op->nx, ny = op->ny, nz = op->nz;
+    g.nt = (nx * ny <= 256) ? 256 : 1024;
+    g.ty = std::min(ny, g.nt / nx);
+    g.n_ytiles = (ny + g.ty - 1) / g.ty;
+    // enough work-groups to give every CU work; each z-chunk re-reads 2R planes
+    const long target = (g.nt == 1024) ? 256 : 1024;
+    int zc = nz;
+    while ((long)g.n_ytiles * w * ((nz + zc - 1) / zc) < target && zc > 8 * RAD) zc = (zc + 1) / 2;
+    g.zchunk = zc;
+    g.n_z = (nz + zc - 1) / zc;
+    g.lds = 2 * (size_t)(nx + 2 * RAD) * (g.ty + 2 * RAD) * sizeof(cplx_t<R>);
+    return g;
+}
+
+template <int RAD, typename R, bool FUSED>
+void fused_launch(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin, cplx_t<R>* pout,
+                  cplx_t<R>* y, int w, const double* shift, const int* skip, const int* kit,
+                  const double2* beta, double2* part, hipStream_t s) {
+    const FusedGeom g = fused_geom<RAD, R>(op, w);
+    Coef<R> cf;
+    for (int m = 0; m < 7; ++m) cf.a[m] = (R)op->coef.a[m];
+    dim3 grid(g.n_ytiles * g.n_z, w);
+    if (g.lds > 65536) {
+        // gfx950 has 160 KB of LDS per CU; dynamic allocations above 64 KB must be opted in
+        static bool done256 = false, done1024 = false;
+        bool& done = (g.nt == 256) ? done256 : done1024;
+        if (!done) {
+            if (g.nt == 256)
+                (void)hipFuncSetAttribute((const void*)k_cocg_apply<RAD, R, 256, FUSED>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            else
+                (void)hipFuncSetAttribute((const void*)k_cocg_apply<RAD, R, 1024, FUSED>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            done = true;
+        }
+    }
+    if (g.nt == 256)
+        hipLaunchKernelGGL((k_cocg_apply<RAD, R, 256, FUSED>), grid, dim3(256), g.lds, s, r, pin,
+                           pout, y, op->nx, op->ny, op->nz, g.ty, g.n_ytiles, g.zchunk, cf,
+                           op->coef.a[0], op->d_v, op->d_wz, shift, skip, kit, beta, part);
+    else
+        hipLaunchKernelGGL((k_cocg_apply<RAD, R, 1024, FUSED>), grid, dim3(1024), g.lds, s, r, pin,
+                           pout, y, op->nx, op->ny, op->nz, g.ty, g.n_ytiles, g.zchunk, cf,
+                           op->coef.a[0], op->d_v, op->d_wz, shift, skip, kit, beta, part);
+}
+
+}  // namespace
+
+int fused_partials(const negf_op* op, int w) {
+    switch (op->R) {
+        case 1: { auto g = fused_geom<1, double>(op, w); return g.n_ytiles * g.n_z; }
+        case 2: { auto g = fused_geom<2, double>(op, w); return g.n_ytiles * g.n_z; }
+        case 3: { auto g = fused_geom<3, double>(op, w); return g.n_ytiles * g.n_z; }
+        case 4: { auto g = fused_geom<4, double>(op, w); return g.n_ytiles * g.n_z; }
+        case 5: { auto g = fused_geom<5, double>(op, w); return g.n_ytiles * g.n_z; }
+        default: { auto g = fused_geom<6, double>(op, w); return g.n_ytiles * g.n_z; }
+    }
+}
+
+template <typename R>
+void launch_cocg_apply(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin,
+                       cplx_t<R>* pout, cplx_t<R>* q, int w, const double* shift, const int* skip,
+                       const int* kit, const double2* beta, double2* part, double2* d_kbc,
+                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (ev0) (void)hipEventRecord(ev0, s);
+    switch (op->R) {
+        case 1: fused_launch<1, R, true>(op, r, pin, pout, q, w, shift, skip, kit, beta, part, s); break;
+        case 2: fused_launch<2, R, true>(op, r, pin, pout, q, w, shift, skip, kit, beta, part, s); break;
+        case 3: fused_launch<3, R, true>(op, r, pin, pout, q, w, shift, skip, kit, beta, part, s); break;
+        case 4: fused_launch<4, R, true>(op, r, pin, pout, q, w, shift, skip, kit, beta, part, s); break;
+        case 5: fused_launch<5, R, true>(op, r, pin, pout, q, w, shift, skip, kit, beta, part, s); break;
+        default: fused_launch<6, R, true>(op, r, pin, pout, q, w, shift, skip, kit, beta, part, s); break;
+    }
+    if (ev1) (void)hipEventRecord(ev1, s);
+    if (op->kb.n_proj > 0) {
+        const DeviceKB& kb = op->kb;
+        dim3 g1(kb.n_proj, (w + 3) / 4);
+        hipLaunchKernelGGL((k_kb_gather<R>), g1, dim3(kThreads), 0, s, pout, op->N, kb.off, kb.idx,
+                           kb.val, kb.n_proj, w, d_kbc, skip);
+        dim3 g2((kb.n_pts + kThreads - 1) / kThreads, w);
+        hipLaunchKernelGGL((k_kb_scatter<R>), g2, dim3(kThreads), 0, s, q, op->N, kb.pts,
+                           kb.pt_off, kb.pt_proj, kb.pt_val, kb.n_pts, kb.n_proj, d_kbc, skip);
+    }
+}
+
+template void launch_cocg_apply<double>(const negf_op*, const double2*, const double2*, double2*,
+                                        double2*, int, const double*, const int*, const int*,
+                                        const double2*, double2*, double2*, hipStream_t,
+                                        hipEvent_t, hipEvent_t);
+template void launch_cocg_apply<float>(const negf_op*, const float2*, const float2*, float2*,
+                                       float2*, int, const double*, const int*, const int*,
+                                       const double2*, double2*, double2*, hipStream_t,
+                                       hipEvent_t, hipEvent_t);
