@@ -175,6 +175,9 @@ def main():
         T, d = P.negf_transmission(op, wire.energies, n_cols=args.block, check=False,
                                    time_matvec=True, col_begin=c0, col_count=args.block,
                                    block_width=args.block, tol=TOL, max_iter=args.max_iter)
+        if d.status not in (0, 4):  # anything but OK / NOT_CONVERGED is a failure
+            raise RuntimeError(f"negf_transmission failed: status {d.status}: "
+                               f"{P.api._lib().negf_last_error().decode()}")
         return T, d
 
     for i in range(args.warmup):

@@ -369,6 +369,7 @@ __global__ void k_f2d(const float2* a, double2* b, int64_t n) {
 extern "C" negf_status negf_apply_operator(negf_op* op, int32_t precision, int32_t n_vec,
                                            const double* shifts, const negf_c64* x, negf_c64* y) {
     g_last_error.clear();
+    (void)hipGetLastError();  // a stale error of an earlier call must not fail this one
     if (!op || !shifts || !x || !y || n_vec < 1 || (precision != NEGF_FP64 && precision != NEGF_MIXED)) {
         set_error("invalid argument to negf_apply_operator");
         return NEGF_E_INVALID_ARG;
@@ -532,6 +533,69 @@ struct MatvecTimer {
     }
 };
 
+// A chunk of solver iterations captured once and replayed: seven small
+// launches per iteration otherwise cost tens of microseconds per iteration.
+// Every kernel reads its iteration state (k, done, alpha, beta, ...) from the
+// device, and chunks start at even iterations, so one capture serves all
+// full chunks of a block.  NEGF_NO_GRAPH=1 launches eagerly instead.
+struct ChunkGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int timer_pairs = 0;
+    bool failed = false;
+    ~ChunkGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+static bool graphs_enabled() {
+    const char* e = getenv("NEGF_NO_GRAPH");
+    return !(e && atoi(e) != 0);
+}
+
+// Runs `issue` (which enqueues one full chunk on s) through the graph; falls
+// back to eager launches when capture is unavailable.
+template <typename F>
+static negf_status run_chunk(ChunkGraph& cg, bool use_graph, hipStream_t s, MatvecTimer* tm,
+                             F issue) {
+    // per-kernel HIP events cannot be timed inside a graph: timed runs go eagerly
+    if (tm->on) use_graph = false;
+    if (use_graph && !cg.failed && !cg.exec) {
+        CHK(tm->flush());
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            const negf_status st = issue();
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(s, &g);
+            if (st != NEGF_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (e == hipSuccess && g &&
+                hipGraphInstantiate(&cg.exec, g, nullptr, nullptr, 0) == hipSuccess) {
+                cg.graph = g;
+                cg.timer_pairs = tm->used;
+                tm->used = 0;  // recorded into the graph, not yet executed
+            } else {
+                if (g) (void)hipGraphDestroy(g);
+                cg.exec = nullptr;
+                cg.failed = true;
+                tm->used = 0;
+                (void)hipGetLastError();
+            }
+        } else {
+            cg.failed = true;
+            (void)hipGetLastError();
+        }
+    }
+    if (use_graph && cg.exec) {
+        HIPCHK(hipGraphLaunch(cg.exec, s));
+        tm->used = cg.timer_pairs;
+        return NEGF_OK;
+    }
+    return issue();
+}
+
 // Output of one multi-shift block.
 struct MSOut {
     double* h_tcol = nullptr;   // [w][ng] host (transmission mode)
@@ -610,23 +674,29 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, c
 
     std::vector<int> h_done(w), h_k(w);
     int k0 = 0;
+    ChunkGraph cg;
+    const bool use_graph = graphs_enabled();
     while (true) {
         const int steps = std::min(ch, d.max_iter - k0);
-        for (int it = 0; it < steps; ++it) {
-            // p ping-pongs so that halo reads of the fused kernel see p_{k-1}
-            const int k = k0 + it;
-            double2* pin = (k & 1) ? p2 : p;
-            double2* pout = (k & 1) ? p : p2;
-            hipEvent_t e0, e1;
-            CHK(tm->next(&e0, &e1));
-            launch_cocg_apply<double>(op, r, pin, pout, q, w, shift, st.done, st.k, st.beta, part_f,
-                                      kbc, s, e0, e1);
-            launch_reduce_alpha(part_f, nblk_f, st, s, op->kb.n_proj ? kbc : nullptr, op->kb.e,
-                                op->kb.n_proj);
-            launch_r_update<double>(r, q, nullptr, nullptr, part, part_nn, st, N, s);
-            launch_store_rows<double>(r, N, w, d_rows, row0, n_rows, ring, ring_len, st, 1, s);
-            launch_reduce_beta_multishift(part, part_nn, nblk, st, s);
-        }
+        auto issue = [&]() -> negf_status {
+            for (int it = 0; it < steps; ++it) {
+                // p ping-pongs so that halo reads of the fused kernel see p_{k-1};
+                // chunks start at even k
+                double2* pin = (it & 1) ? p2 : p;
+                double2* pout = (it & 1) ? p : p2;
+                hipEvent_t e0, e1;
+                CHK(tm->next(&e0, &e1));
+                launch_cocg_apply<double>(op, r, pin, pout, q, w, shift, st.done, st.k, st.beta,
+                                          part_f, kbc, s, e0, e1);
+                launch_reduce_alpha(part_f, nblk_f, st, s, op->kb.n_proj ? kbc : nullptr,
+                                    op->kb.e, op->kb.n_proj);
+                launch_r_update<double>(r, q, nullptr, nullptr, part, part_nn, st, N, s);
+                launch_store_rows<double>(r, N, w, d_rows, row0, n_rows, ring, ring_len, st, 1, s);
+                launch_reduce_beta_multishift(part, part_nn, nblk, st, s);
+            }
+            return NEGF_OK;
+        };
+        CHK(run_chunk(cg, use_graph && steps == ch, s, tm, issue));
         // fold the chunk's iterations into X and P of every energy
         launch_chunk_coef(st, k0, cx, cp, xi_a, carry, active, s);
         launch_gemm_xp(ring, ring_len, w, n_rows, k0, st, cx, cp, xi_a, active, X, P, s);
@@ -691,6 +761,8 @@ struct PEOut {
     int* h_refine = nullptr;   // [w] refinement steps
 };
 
+static constexpr int kInnerChunk = 16;
+
 template <typename R>
 static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, const int* cols,
                                         const double2* d_rhs, const double* item_e,
@@ -743,6 +815,8 @@ static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, c
 
     std::vector<int> h_done(w), h_odone(w), h_k(w), iters(w, 0), refine(w, 0);
     int outer = 0;
+    ChunkGraph cg;
+    const bool use_graph = graphs_enabled();
     const double inner_tol = (sizeof(R) == 8) ? 0.5 * d.tol : 2e-6;
     while (true) {
         if (outer > 0) {
@@ -764,20 +838,23 @@ static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, c
         launch_reduce_init(part, part_nn, nblk, st, odone, s);
         int k_host = 0;
         while (true) {
-            const int steps = std::min(16, d.max_iter - k_host);
-            for (int it = 0; it < steps; ++it) {
-                const int k = k_host + it;
-                cplx_t<R>* pin = (k & 1) ? p2 : p;
-                cplx_t<R>* pout = (k & 1) ? p : p2;
-                hipEvent_t e0, e1;
-                CHK(tm->next(&e0, &e1));
-                launch_cocg_apply<R>(op, r, pin, pout, q, w, shift, st.done, st.k, st.beta, part_f,
-                                     kbc, s, e0, e1);
-                launch_reduce_alpha(part_f, nblk_f, st, s, op->kb.n_proj ? kbc : nullptr, op->kb.e,
-                                    op->kb.n_proj);
-                launch_r_update<R>(r, q, pout, dsol, part, part_nn, st, N, s);
-                launch_reduce_beta_single(part, part_nn, nblk, st, inner_tol, s);
-            }
+            const int steps = std::min(kInnerChunk, d.max_iter - k_host);
+            auto issue = [&]() -> negf_status {
+                for (int it = 0; it < steps; ++it) {
+                    cplx_t<R>* pin = (it & 1) ? p2 : p;  // chunks start at even k
+                    cplx_t<R>* pout = (it & 1) ? p : p2;
+                    hipEvent_t e0, e1;
+                    CHK(tm->next(&e0, &e1));
+                    launch_cocg_apply<R>(op, r, pin, pout, q, w, shift, st.done, st.k, st.beta,
+                                         part_f, kbc, s, e0, e1);
+                    launch_reduce_alpha(part_f, nblk_f, st, s, op->kb.n_proj ? kbc : nullptr,
+                                        op->kb.e, op->kb.n_proj);
+                    launch_r_update<R>(r, q, pout, dsol, part, part_nn, st, N, s);
+                    launch_reduce_beta_single(part, part_nn, nblk, st, inner_tol, s);
+                }
+                return NEGF_OK;
+            };
+            CHK(run_chunk(cg, use_graph && steps == kInnerChunk, s, tm, issue));
             HIPCHK(hipGetLastError());
             k_host += steps;
             HIPCHK(hipMemcpyAsync(h_done.data(), st.done, w * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1036,6 +1113,7 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
 extern "C" negf_status negf_transmission(negf_op* op, const negf_opts* opts, int32_t n_e,
                                          const double* energies, double* T, negf_diag* diag) {
     g_last_error.clear();
+    (void)hipGetLastError();  // a stale error of an earlier call must not fail this one
     if (!op) {
         set_error("null op");
         return NEGF_E_INVALID_ARG;
@@ -1188,6 +1266,7 @@ extern "C" negf_status negf_solve_columns(negf_op* op, const negf_opts* opts, in
                                           int32_t n_rows, const int32_t* row_idx, negf_c64* out,
                                           int32_t* item_status) {
     g_last_error.clear();
+    (void)hipGetLastError();
     if (!op) {
         set_error("null op");
         return NEGF_E_INVALID_ARG;
@@ -1277,6 +1356,7 @@ extern "C" negf_status negf_transmission_grad(negf_op* op, const negf_opts* opts
                                               const double* energies, const double* weights,
                                               double* dL_dV, double* T) {
     g_last_error.clear();
+    (void)hipGetLastError();
     if (!op) {
         set_error("null op");
         return NEGF_E_INVALID_ARG;
