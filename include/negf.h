@@ -174,6 +174,23 @@ negf_status negf_solve_columns(negf_op* op, const negf_opts* opts, int32_t n_e,
 negf_status negf_transmission(negf_op* op, const negf_opts* opts, int32_t n_e,
                               const double* energies, double* T, negf_diag* diag);
 
+/* Batched T(E) over n_ops independent junctions (each its own operator, grid
+ * and energy grid), submitted together so that the device overlaps them: the
+ * junctions are taken largest-first by up to max_concurrent host workers, each
+ * driving one junction at a time on that operator's own stream (the chunks of
+ * iterations are HIP-graph replays).  Each op's workspace is released when its
+ * junction finishes.  Equivalent to calling negf_transmission(ops[i], opts,
+ * n_e[i], energies[i], T[i], NULL) for every i; the per-op results are
+ * bit-identical to that.
+ *   ops         n_ops operators (distinct; each used by one worker at a time)
+ *   n_e, energies, T   per-op energy counts, host energy arrays, host outputs
+ *   status      n_ops host per-op negf_status codes (nullable)
+ *   max_concurrent   workers (0 -> 4)
+ * Returns the first non-OK per-op status, or NEGF_OK. */
+negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* ops, const negf_opts* opts,
+                                    const int32_t* n_e, const double* const* energies,
+                                    double* const* T, int32_t* status, int32_t max_concurrent);
+
 /* Adjoint gradient of L = sum_e weights[e] T(E_e) with respect to the local
  * potential: dL_dV[r] = sum_e w_e 8 Re sum_{j in R} W_R,j lambda_j(r) g_j(r),
  * with g_j = A^-1 e_j and lambda_j = A^-1 (W_L o conj(g_j)) solved with the

@@ -27,6 +27,7 @@ EXPORTS = (
     "negf_apply_operator",
     "negf_solve_columns",
     "negf_transmission",
+    "negf_transmission_batch",
     "negf_transmission_grad",
     "negf_destroy",
     "negf_last_error",
@@ -83,12 +84,14 @@ def load(path: str | None = None):
     lib.negf_transmission.argtypes = [vp, C.POINTER(negf_opts), C.c_int32, vp, vp,
                                       C.POINTER(negf_diag)]
     lib.negf_transmission_grad.argtypes = [vp, C.POINTER(negf_opts), C.c_int32, vp, vp, vp, vp]
+    lib.negf_transmission_batch.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(negf_opts),
+                                            vp, C.POINTER(vp), C.POINTER(vp), vp, C.c_int32]
     lib.negf_destroy.argtypes = [vp]
     lib.negf_destroy.restype = None
     lib.negf_last_error.restype = C.c_char_p
     lib.negf_version.restype = C.c_char_p
     for name in ("negf_build_operator", "negf_apply_operator", "negf_solve_columns",
-                 "negf_transmission", "negf_transmission_grad"):
+                 "negf_transmission", "negf_transmission_grad", "negf_transmission_batch"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

@@ -226,3 +226,22 @@ def negf_transmission_grad(op: Operator, energies, weights, dL_dV=None, want_T=T
     _check(_lib().negf_transmission_grad(op.handle, C.byref(o), energies.size, _ptr(energies),
                                          _ptr(weights), _ptr(dL_dV), _ptr(T)))
     return dL_dV, T
+
+
+def negf_transmission_batch(ops, energies_list, max_concurrent=0, check=True, **opts):
+    """T(E) for many junctions at once; returns (list of T arrays, statuses)."""
+    n = len(ops)
+    es = [np.ascontiguousarray(e, dtype=np.float64) for e in energies_list]
+    Ts = [np.zeros(e.size) for e in es]
+    n_e = np.array([e.size for e in es], np.int32)
+    handles = (C.c_void_p * n)(*[op.handle.value if hasattr(op.handle, "value") else op.handle
+                                 for op in ops])
+    e_ptrs = (C.c_void_p * n)(*[e.ctypes.data for e in es])
+    t_ptrs = (C.c_void_p * n)(*[t.ctypes.data for t in Ts])
+    status = np.zeros(n, np.int32)
+    o = _opts(**opts)
+    st = _lib().negf_transmission_batch(n, handles, C.byref(o), _ptr(n_e), e_ptrs, t_ptrs,
+                                        _ptr(status), int(max_concurrent))
+    if check:
+        _check(st)
+    return Ts, status

@@ -8,7 +8,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <chrono>
+#include <atomic>
 #include <map>
+#include <mutex>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -64,14 +67,14 @@ negf_status hip_fail(hipError_t e, const char* what, int line) {
 
 // Test hook: NEGF_TEST_FAIL_ALLOC=k makes the k-th workspace allocation of the
 // process fail (exercises the out-of-memory path without exhausting HBM).
-static long g_alloc_count = 0;
+static std::atomic<long> g_alloc_count{0};
 
 static negf_status dev_alloc(void** p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) bytes = 256;
-    ++g_alloc_count;
+    const long n_alloc = ++g_alloc_count;
     if (const char* env = getenv("NEGF_TEST_FAIL_ALLOC")) {
-        if (atol(env) == g_alloc_count) {
+        if (atol(env) == n_alloc) {
             set_error("allocation of %zu bytes failed (test hook)", bytes);
             return NEGF_E_OUT_OF_MEMORY;
         }
@@ -1362,4 +1365,81 @@ extern "C" negf_status negf_transmission_grad(negf_op* op, const negf_opts* opts
         return NEGF_E_INVALID_ARG;
     }
     return grad_impl(op, opts, n_e, energies, weights, dL_dV, T);
+}
+
+// ---------------------------------------------------------------------------
+// negf_transmission_batch
+// ---------------------------------------------------------------------------
+static void release_workspace(negf_op* op) {
+    (void)hipStreamSynchronize(op->own_stream);
+    for (auto& b : op->bufs) {
+        if (b.ptr) (void)hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+}
+
+extern "C" negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* ops,
+                                               const negf_opts* opts, const int32_t* n_e,
+                                               const double* const* energies, double* const* T,
+                                               int32_t* status, int32_t max_concurrent) {
+    g_last_error.clear();
+    (void)hipGetLastError();
+    if (n_ops < 1 || !ops || !n_e || !energies || !T) {
+        set_error("invalid batch arguments");
+        return NEGF_E_INVALID_ARG;
+    }
+    for (int i = 0; i < n_ops; ++i) {
+        if (!ops[i] || !energies[i] || !T[i] || n_e[i] < 1) {
+            set_error("batch entry %d is invalid", i);
+            return NEGF_E_INVALID_ARG;
+        }
+        for (int j = 0; j < i; ++j)
+            if (ops[j] == ops[i]) {
+                set_error("batch entries %d and %d share an operator", j, i);
+                return NEGF_E_INVALID_ARG;
+            }
+    }
+    if (opts && opts->stream) {
+        set_error("the batch runs every junction on its operator's own stream; opts->stream must be NULL");
+        return NEGF_E_INVALID_ARG;
+    }
+    // largest first: work ~ points x source columns x energies
+    std::vector<int> order(n_ops);
+    std::vector<double> cost(n_ops);
+    for (int i = 0; i < n_ops; ++i) {
+        order[i] = i;
+        const negf_op* op = ops[i];
+        cost[i] = (double)op->N * (double)(op->zr1 - op->zr0) * op->nx * op->ny * n_e[i];
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    const int n_workers = std::max(1, std::min(n_ops, max_concurrent > 0 ? max_concurrent : 4));
+    std::vector<negf_status> st(n_ops, NEGF_OK);
+    std::vector<std::string> msg(n_ops);
+    std::atomic<int> next{0};
+    int device = 0;
+    HIPCHK(hipGetDevice(&device));
+    auto worker = [&]() {
+        (void)hipSetDevice(device);
+        while (true) {
+            const int t = next.fetch_add(1);
+            if (t >= n_ops) break;
+            const int i = order[t];
+            st[i] = transmission_impl(ops[i], opts, n_e[i], energies[i], T[i], nullptr);
+            if (st[i] != NEGF_OK) msg[i] = g_last_error;
+            release_workspace(ops[i]);
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int k = 0; k < n_workers; ++k) pool.emplace_back(worker);
+    for (auto& th : pool) th.join();
+    negf_status first = NEGF_OK;
+    for (int i = 0; i < n_ops; ++i) {
+        if (status) status[i] = st[i];
+        if (st[i] != NEGF_OK && first == NEGF_OK) {
+            first = st[i];
+            set_error("junction %d: %s", i, msg[i].c_str());
+        }
+    }
+    return first;
 }

@@ -1,0 +1,61 @@
+"""Batched junctions: negf_transmission_batch equals per-junction calls bit for
+bit, and matches the oracle on the small ones."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import make_custom, make_junctions
+
+pytestmark = pytest.mark.gpu
+
+
+def _junctions():
+    out = []
+    for k, (n, nz, R, ncap, ne) in enumerate([(8, 28, 2, 6, 5), (10, 36, 3, 6, 9), (9, 30, 4, 7, 3),
+                                                (12, 40, 2, 8, 7), (8, 24, 1, 5, 6)]):
+        h = 0.5
+        c = (n + 1) * h / 2
+        wells = [(c + 0.2 * k, c - 0.1, 5.0 + k, 0.3 + 0.05 * k), (c, c, nz * h * 0.6, 0.4)]
+        out.append(make_custom(n, n, nz, h, R, ncap, np.linspace(0.2, 1.0, ne), wells=wells,
+                               name=f"j{k}"))
+    return out
+
+
+def test_batch_matches_single_calls_and_oracle(gpu_lib):
+    import paper_1401_0782_amd as P
+
+    js = _junctions()
+    ops = [P.operator_from_wire(j) for j in js]
+    Tb, st = P.negf_transmission_batch(ops, [j.energies for j in js], max_concurrent=3, tol=1e-12)
+    assert np.all(st == 0)
+    for j, op, T in zip(js, ops, Tb):
+        Ts = P.negf_transmission(op, j.energies, tol=1e-12)
+        assert np.array_equal(T, Ts)
+    for j, T in zip(js[:3], Tb[:3]):
+        assert np.max(np.abs(T - O.transmission(j, method="dense"))) <= 1e-8
+
+
+def test_batch_uneven_wire_junctions(gpu_lib):
+    """Eight junctions of the batched workload (16^2 x 64 .. 40^2 x 160), first
+    8 source columns each, every energy: batch equals single calls."""
+    import paper_1401_0782_amd as P
+
+    js = make_junctions(64)[:8]
+    ops = [P.operator_from_wire(j) for j in js]
+    kw = dict(tol=1e-10, col_begin=0, col_count=8, block_width=8)
+    Tb, st = P.negf_transmission_batch(ops, [j.energies for j in js], max_concurrent=4, **kw)
+    assert np.all(st == 0)
+    for j, op, T in zip(js, ops, Tb):
+        assert np.all(T >= 0)
+        assert np.array_equal(T, P.negf_transmission(op, j.energies, **kw))
+
+
+def test_batch_rejects_shared_operator(gpu_lib):
+    import paper_1401_0782_amd as P
+    from paper_1401_0782_amd import NegfError
+
+    j = _junctions()[0]
+    op = P.operator_from_wire(j)
+    with pytest.raises(NegfError, match="share"):
+        P.negf_transmission_batch([op, op], [j.energies, j.energies])
