@@ -98,7 +98,7 @@ typedef struct {
     double tol;          /* relative residual per (column, energy); FP64 path:
                             COCG residual estimate; mixed path: true FP64
                             residual ||b - A x|| / ||b||.  0 -> 1e-10 */
-    int32_t max_iter;    /* Krylov iterations per run; 0 -> 20000 */
+    int32_t max_iter;    /* Krylov iterations per run; 0 -> 100000 */
     int32_t block_width; /* columns (or items) per block; 0 -> auto */
     int32_t shift_group; /* energies per multi-shift run; 0 -> all */
     int32_t max_refine;  /* mixed: outer refinement steps; 0 -> 8 */

@@ -420,7 +420,7 @@ static negf_status read_opts(const negf_opts* o, Defaults* d) {
     d->core = o ? o->core : NEGF_CORE_AUTO;
     d->direction = o ? o->direction : NEGF_DIR_RL;
     d->tol = (o && o->tol > 0) ? o->tol : 1e-10;
-    d->max_iter = (o && o->max_iter > 0) ? o->max_iter : 20000;
+    d->max_iter = (o && o->max_iter > 0) ? o->max_iter : 100000;
     d->block_width = (o && o->block_width > 0) ? o->block_width : 0;
     d->shift_group = (o && o->shift_group > 0) ? o->shift_group : 0;
     d->max_refine = (o && o->max_refine > 0) ? o->max_refine : 8;

@@ -1,0 +1,81 @@
+"""Full-size checks on the 32x32x192 R=6 wire with projectors, in the launch
+configuration bench.py times (64-column multi-shift blocks, all 256 energies).
+
+The oracle cannot solve every item at this size in seconds, so the checks are
+(i) identities that hold at any size, on every (column, energy) of the block,
+and (ii) the stored oracle samples in tests/golden (when present)."""
+
+import json
+import pathlib
+
+import numpy as np
+import pytest
+
+from workloads import left_support, make_wire, rhs_columns
+
+pytestmark = pytest.mark.gpu
+GOLDEN = pathlib.Path(__file__).parent / "golden" / "wire32x32x192_samples.json"
+
+
+@pytest.fixture(scope="module")
+def wire2():
+    return make_wire(2)
+
+
+@pytest.fixture(scope="module")
+def op2(gpu_lib, wire2):
+    import paper_1401_0782_amd as P
+
+    return P.operator_from_wire(wire2)
+
+
+def test_optical_theorem_and_bounds_full_block(op2, wire2):
+    """Per column and energy: sum_i W_i |g_i|^2 = -Im g_jj (from A = E - H + iW,
+    Eq. 4, with H real), and t_j <= 4 W_R,j (-Im g_jj); t_j from the
+    transmission call equals the one recomputed from the returned rows."""
+    import paper_1401_0782_amd as P
+
+    w = wire2
+    per = w.nx * w.ny
+    cols = rhs_columns(w)[:64]
+    L = left_support(w)
+    Rr = rhs_columns(w)
+    rows = np.concatenate([L, Rr]).astype(np.int32)
+    W = np.concatenate([np.repeat(w.cap_left, per)[L], np.repeat(w.cap_right, per)[Rr]])
+    wr = np.repeat(w.cap_right, per)
+    out, st = P.negf_solve_columns(op2, w.energies, rhs_idx=cols, row_idx=rows, tol=1e-10,
+                                   core=P.NEGF_CORE_MULTISHIFT, block_width=64)
+    assert np.all(st == 0)
+    pos = {int(r): k for k, r in enumerate(rows)}
+    jj = np.array([pos[int(j)] for j in cols])
+    g_jj = out[:, np.arange(64), jj]                       # [e][c]
+    lhs = np.einsum("ecr,r->ec", np.abs(out) ** 2, W)      # sum_i W_i |g_i|^2
+    rel = np.abs(lhs + g_jj.imag) / np.abs(g_jj)
+    assert rel.max() < 1e-7, rel.max()
+    tL = 4.0 * wr[cols][None, :] * np.einsum("ecr,r->ec", np.abs(out[:, :, :len(L)]) ** 2,
+                                             W[:len(L)])
+    assert np.all(tL >= 0) and np.all(tL <= 4.0 * wr[cols][None, :] * (-g_jj.imag) * (1 + 1e-12))
+    T, d = P.negf_transmission(op2, w.energies, n_cols=64, col_begin=0, col_count=64,
+                               block_width=64, tol=1e-10)
+    assert np.max(np.abs(d.t_col - tL)) <= 1e-12 * max(1.0, tL.max())
+    assert np.allclose(T, d.t_col.sum(axis=1), rtol=1e-14, atol=0)
+
+
+@pytest.mark.skipif(not GOLDEN.exists(), reason="oracle samples not generated")
+def test_oracle_samples(op2, wire2):
+    """t_j(E) at oracle-solved (column, energy) samples (true residual 1e-12)."""
+    import paper_1401_0782_amd as P
+
+    data = json.loads(GOLDEN.read_text())
+    cols = rhs_columns(wire2)
+    by_block = {}
+    for smp in data["samples"]:
+        assert int(cols[smp["col"]]) == smp["grid_index"]
+        by_block.setdefault(smp["col"] // 64, []).append(smp)
+    for blk, smps in sorted(by_block.items()):
+        # the bench's launch configuration: one 64-column block, all 256 energies
+        T, d = P.negf_transmission(op2, wire2.energies, n_cols=64, col_begin=64 * blk,
+                                   col_count=64, block_width=64, tol=1e-11)
+        for smp in smps:
+            t = d.t_col[smp["e_index"], smp["col"] - 64 * blk]
+            assert abs(t - smp["t_col"]) <= 1e-8 * max(1.0, abs(smp["t_col"])), (smp, t)
