@@ -20,7 +20,7 @@ LIB = PKG / "libnegf.so"
 
 ARCH = "gfx950"
 CXXFLAGS = [
-    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 instructions stay out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",

@@ -639,6 +639,7 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, c
     CHK(ws(op, WS_KBC, (size_t)w * std::max(1, op->kb.n_proj), &kbc));
     CHK(ws(op, WS_SHIFT, (size_t)w, &shift));
     CHK(ws(op, WS_COLJ, (size_t)w, &d_cols));
+    CHK(ws_get(op, WS_SINK, (size_t)w * op->nx * op->ny * sizeof(double2), &op->d_sink));
     CHK(ws(op, WS_RING, (size_t)ring_len * w * n_rows, &ring));
     CHK(ws(op, WS_XS, (size_t)w * ng * n_rows, &X));
     CHK(ws(op, WS_PS, (size_t)w * ng * n_rows, &P));
@@ -785,6 +786,7 @@ static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, c
     CHK(ws(op, WS_X, (size_t)w * N, &dsol));
     CHK(ws(op, WS_B, (size_t)w * N, &b64));
     CHK(ws(op, WS_PART3, (size_t)w * nblk_f, &part_f));
+    CHK(ws_get(op, WS_SINK, (size_t)w * op->nx * op->ny * sizeof(double2), &op->d_sink));
     CHK(ws(op, WS_X64, (size_t)w * N, &x64));
     CHK(ws(op, WS_R64, (size_t)w * N, &r64));
     CHK(ws(op, WS_Q64, (size_t)w * N, &q64));

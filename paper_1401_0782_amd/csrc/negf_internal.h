@@ -78,6 +78,7 @@ struct negf_op {
     double* d_wz = nullptr;      // [nz] W_L + W_R per plane
     double* d_wl = nullptr;      // [nz]
     double* d_wr = nullptr;      // [nz]
+    void* d_sink = nullptr;      // discard target of the whole-plane stencil kernel (workspace)
     DeviceKB kb;
     hipStream_t own_stream = nullptr;
     std::vector<Buffer> bufs;    // workspace, indexed by WorkSlot
@@ -97,7 +98,7 @@ enum WorkSlot {
     WS_R = 0, WS_P, WS_Q, WS_X, WS_B, WS_R64, WS_X64, WS_Q64,
     WS_PART, WS_PART2, WS_PART3, WS_KBC, WS_SHIFT, WS_COLJ,
     WS_STATE, WS_HIST, WS_PI, WS_GAMMA, WS_TRI, WS_TPART, WS_TCOL, WS_ROWS,
-    WS_ROWW, WS_RING, WS_XS, WS_PS, WS_COEF, WS_MISC, WS_COUNT
+    WS_ROWW, WS_RING, WS_XS, WS_PS, WS_COEF, WS_MISC, WS_SINK, WS_COUNT
 };
 negf_status ws_get(negf_op* op, int slot, size_t bytes, void** out);
 

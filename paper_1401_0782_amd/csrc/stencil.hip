@@ -376,9 +376,13 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
         if (own && zz >= 0 && zz < nz) val = p_at((int64_t)zz * plane + col_off);
         q[d] = val;
     }
-    // prefetch of the lead plane z0 + RAD
+    // prefetch of the lead plane z0 + RAD and of V on the centre plane z0.
+    // Vector memory counters retire in order, so every per-lane load the
+    // plane step consumes is issued one step ahead: a load issued and used in
+    // the same step would also wait for the prefetch behind it.
     cplx_t<R> nr, np;
     nr.x = nr.y = np.x = np.y = 0;
+    double v_next = own ? v[(int64_t)z0 * plane + col_off] : 0.0;
     {
         const int zl = z0 + RAD;
         if (own && zl < nz) {
@@ -395,6 +399,7 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
     __syncthreads();
     for (int z = z0; z < z1; ++z) {
         cplx_t<R>* tile = (z & 1) ? tile1 : tile0;
+        const double v_cur = v_next;
         // lead plane z + RAD from the prefetched values
         {
             cplx_t<R> lead;
@@ -408,7 +413,7 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
             }
             q[2 * RAD] = lead;
         }
-        // prefetch plane z + RAD + 1
+        // prefetch plane z + RAD + 1 and V of plane z + 1
         {
             const int zl = z + RAD + 1;
             nr.x = nr.y = np.x = np.y = 0;
@@ -421,6 +426,7 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
                     np = pin[gi];
                 }
             }
+            if (own && z + 1 < z1) v_next = v[(int64_t)(z + 1) * plane + col_off];
         }
         // stage the centre plane
         if (own) {
@@ -443,7 +449,7 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
         if (own) {
             const int64_t gi = (int64_t)z * plane + col_off;
             const cplx_t<R> xi = q[RAD];
-            const R dr = (R)(e_c - v[gi]);
+            const R dr = (R)(e_c - v_cur);
             const R di = (R)wz[z];
             R ax = dr * xi.x - di * xi.y;
             R ay = dr * xi.y + di * xi.x;
@@ -494,9 +500,164 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
     }
 }
 
+// Whole-plane variant of k_cocg_apply: the work-group is exactly one z-plane
+// of one column (blockDim = nx*ny <= 1024, a multiple of the wave size), so
+// there is no y-halo and every thread owns a point.  Two things keep the
+// in-order vector-memory queue from draining every plane:
+//  * all global loads and stores are unconditional (plane indices clamped,
+//    out-of-grid values discarded by selection, stores that belong to no plane
+//    go to a small sink buffer), so no execution-mask branch surrounds them;
+//  * the z-queue is unrolled 2R+1 ways: slot (u + d) mod (2R+1) holds plane
+//    z + d - R at unrolled step u, so no register is rewritten while a store
+//    that reads it may still be pending.
+template <int RAD, typename R, bool FUSED>
+__global__ __launch_bounds__(1024) void k_cocg_plane(
+    const cplx_t<R>* __restrict__ r, const cplx_t<R>* __restrict__ pin, cplx_t<R>* __restrict__ pout,
+    cplx_t<R>* __restrict__ y, cplx_t<R>* __restrict__ sink, int nx, int ny, int nz, int zchunk,
+    Coef<R> cf, double a0, const double* __restrict__ v, const double* __restrict__ wz,
+    const double* __restrict__ shift, const int* __restrict__ skip, const int* __restrict__ kit,
+    const double2* __restrict__ beta, double2* __restrict__ part) {
+    constexpr int Q = 2 * RAD + 1;
+    extern __shared__ unsigned char smem_raw[];
+    const int c = blockIdx.y;
+    if (skip && skip[c]) return;
+    const int z0 = blockIdx.x * zchunk;
+    const int z1 = min(nz, z0 + zchunk);
+    const int pitch = nx + 2 * RAD;
+    const int lrows = ny + 2 * RAD;
+    cplx_t<R>* tile0 = reinterpret_cast<cplx_t<R>*>(smem_raw);
+    cplx_t<R>* tile1 = tile0 + pitch * lrows;
+    const int64_t plane = (int64_t)nx * ny;
+    const int64_t co = (int64_t)c * plane * nz;
+    const int tid = threadIdx.x;
+    const int lx = tid % nx, ly = tid / nx;
+    const int64_t col_off = tid;  // = ly * nx + lx
+    const int lds_at = (ly + RAD) * pitch + RAD + lx;
+    cplx_t<R>* my_sink = sink + (int64_t)c * plane + col_off;
+    const double e_c = shift[c] + a0;
+    const bool first = FUSED ? (kit[c] == 0) : true;
+    const double2 bb = FUSED ? beta[c] : make_double2(0.0, 0.0);
+    const R bx = (R)bb.x, byy = (R)bb.y;
+    const R zero = 0;
+
+    auto make_p = [&](cplx_t<R> rv, cplx_t<R> pv) -> cplx_t<R> {
+        if (!FUSED) return pv;
+        cplx_t<R> o;
+        o.x = first ? rv.x : rv.x + bx * pv.x - byy * pv.y;
+        o.y = first ? rv.y : rv.y + bx * pv.y + byy * pv.x;
+        return o;
+    };
+    auto load_plane = [&](int zz, cplx_t<R>& rv, cplx_t<R>& pv) {
+        const int zc = min(max(zz, 0), nz - 1);
+        const int64_t gi = co + (int64_t)zc * plane + col_off;
+        if (FUSED) rv = r[gi];
+        pv = pin[gi];
+    };
+
+    for (int k = tid; k < 2 * pitch * lrows; k += blockDim.x) {
+        tile0[k].x = 0;
+        tile0[k].y = 0;
+    }
+    cplx_t<R> q[Q];
+#pragma unroll
+    for (int d = 0; d < 2 * RAD; ++d) {
+        const int zz = z0 + d - RAD;
+        cplx_t<R> rv, pv;
+        rv.x = rv.y = pv.x = pv.y = 0;
+        load_plane(zz, rv, pv);
+        const cplx_t<R> pp = make_p(rv, pv);
+        const bool in = zz >= 0 && zz < nz;
+        q[d].x = in ? pp.x : zero;
+        q[d].y = in ? pp.y : zero;
+    }
+    cplx_t<R> nr, np;
+    nr.x = nr.y = np.x = np.y = 0;
+    load_plane(z0 + RAD, nr, np);
+    double v_next = v[(int64_t)z0 * plane + col_off];
+    double dot_x = 0.0, dot_y = 0.0;
+    __syncthreads();
+
+    // Q plane steps per trip with the queue rotated by u (a constant after
+    // unrolling); the last trip runs past z1 with its loads clamped, its
+    // stores sunk and its dot products dropped
+    for (int zt = z0; zt < z1; zt += Q) {
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+            const int z = zt + u;
+            cplx_t<R>* tile = (z & 1) ? tile1 : tile0;
+            const double v_cur = v_next;
+            {
+                const cplx_t<R> pp = make_p(nr, np);
+                const bool in = z + RAD < nz;
+                q[(u + 2 * RAD) % Q].x = in ? pp.x : zero;
+                q[(u + 2 * RAD) % Q].y = in ? pp.y : zero;
+            }
+            load_plane(z + RAD + 1, nr, np);
+            v_next = v[(int64_t)min(z + 1, nz - 1) * plane + col_off];
+            const cplx_t<R> xi = q[(u + RAD) % Q];
+            tile[lds_at] = xi;
+            const bool live = z < z1;
+            const int64_t gz = co + (int64_t)min(z, nz - 1) * plane + col_off;
+            if (FUSED) {
+                cplx_t<R>* dst = live ? pout + gz : my_sink;
+                *dst = xi;
+            }
+            __syncthreads();
+            const R dr = (R)(e_c - v_cur);
+            const R di = (R)wz[min(z, nz - 1)];
+            R ax = dr * xi.x - di * xi.y;
+            R ay = dr * xi.y + di * xi.x;
+            const cplx_t<R>* row = tile + lds_at;
+#pragma unroll
+            for (int m = 1; m <= RAD; ++m) {
+                const cplx_t<R> a0v = row[-m], a1v = row[m];
+                const cplx_t<R> b0v = row[-m * pitch], b1v = row[m * pitch];
+                const cplx_t<R> c0v = q[(u + RAD - m) % Q], c1v = q[(u + RAD + m) % Q];
+                ax += cf.a[m] * ((a0v.x + a1v.x) + (b0v.x + b1v.x) + (c0v.x + c1v.x));
+                ay += cf.a[m] * ((a0v.y + a1v.y) + (b0v.y + b1v.y) + (c0v.y + c1v.y));
+            }
+            cplx_t<R> o;
+            o.x = ax;
+            o.y = ay;
+            cplx_t<R>* ydst = live ? y + gz : my_sink;
+            *ydst = o;
+            if (FUSED) {
+                const double dx = (double)xi.x * ax - (double)xi.y * ay;
+                const double dy = (double)xi.x * ay + (double)xi.y * ax;
+                dot_x += live ? dx : 0.0;
+                dot_y += live ? dy : 0.0;
+            }
+        }
+    }
+    if (FUSED) {
+        __syncthreads();
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            dot_x += __shfl_xor(dot_x, o, 64);
+            dot_y += __shfl_xor(dot_y, o, 64);
+        }
+        double* red = reinterpret_cast<double*>(smem_raw);
+        const int wave = tid / 64;
+        if (tid % 64 == 0) {
+            red[2 * wave] = dot_x;
+            red[2 * wave + 1] = dot_y;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double sx = 0.0, sy = 0.0;
+            for (int wv = 0; wv < (int)blockDim.x / 64; ++wv) {
+                sx += red[2 * wv];
+                sy += red[2 * wv + 1];
+            }
+            part[(int64_t)c * gridDim.x + blockIdx.x] = make_double2(sx, sy);
+        }
+    }
+}
+
 namespace {
 
 struct FusedGeom {
+    bool whole_plane;  // k_cocg_plane: one full plane per work-group
     int nt, ty, n_ytiles, zchunk, n_z;
     size_t lds;
 };
@@ -505,6 +666,23 @@ template <int RAD, typename R>
 FusedGeom fused_geom(const negf_op* op, int w) {
     FusedGeom g;
     const int nx = op->nx, ny = op->ny, nz = op->nz;
+    const int pts = nx * ny;
+    g.whole_plane = pts <= 1024 && pts % 64 == 0 && getenv("NEGF_NO_PLANE_KERNEL") == nullptr;
+    if (g.whole_plane) {
+        g.nt = pts;
+        g.ty = ny;
+        g.n_ytiles = 1;
+        // z-chunks: enough work-groups for every CU, each a multiple of the
+        // 2R+1 unrolled steps (the last trip of a chunk runs whole)
+        constexpr int Q = 2 * RAD + 1;
+        int nzc = std::max(1, (256 + w - 1) / w);
+        int zc = (nz + nzc - 1) / nzc;
+        zc = std::max(Q, ((zc + Q - 1) / Q) * Q);
+        g.zchunk = zc;
+        g.n_z = (nz + zc - 1) / zc;
+        g.lds = 2 * (size_t)(nx + 2 * RAD) * (ny + 2 * RAD) * sizeof(cplx_t<R>);
+        return g;
+    }
     g.nt = (nx * ny <= 256) ? 256 : 1024;
     g.ty = std::min(ny, g.nt / nx);
     g.n_ytiles = (ny + g.ty - 1) / g.ty;
@@ -526,6 +704,21 @@ void fused_launch(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin, c
     Coef<R> cf;
     for (int m = 0; m < 7; ++m) cf.a[m] = (R)op->coef.a[m];
     dim3 grid(g.n_ytiles * g.n_z, w);
+    if (g.whole_plane) {
+        if (g.lds > 65536) {
+            static bool done_plane = false;
+            if (!done_plane) {
+                (void)hipFuncSetAttribute((const void*)k_cocg_plane<RAD, R, FUSED>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                done_plane = true;
+            }
+        }
+        hipLaunchKernelGGL((k_cocg_plane<RAD, R, FUSED>), grid, dim3(g.nt), g.lds, s, r, pin, pout,
+                           y, reinterpret_cast<cplx_t<R>*>(op->d_sink), op->nx, op->ny, op->nz,
+                           g.zchunk, cf, op->coef.a[0], op->d_v, op->d_wz, shift, skip, kit, beta,
+                           part);
+        return;
+    }
     if (g.lds > 65536) {
         // gfx950 has 160 KB of LDS per CU; dynamic allocations above 64 KB must be opted in
         static bool done256 = false, done1024 = false;
