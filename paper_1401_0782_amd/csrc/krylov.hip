@@ -184,26 +184,15 @@ __global__ __launch_bounds__(kT) void k_r_update(cplx_t<R>* __restrict__ r,
 //   scaled residual polynomial value pih = pi * s_0 / s_k, with
 //   pi_{k+1} = (1 + alpha_k delta) pi_k + (alpha_k beta_{k-1}/alpha_{k-1}) (pi_k - pi_{k-1}),
 //   so that ||r^delta_k|| / ||b|| = 1 / |pih_k|.
-__global__ __launch_bounds__(kT) void k_reduce_beta_ms(const double2* __restrict__ part_rr,
-                                                       const double* __restrict__ part_nn,
-                                                       int nblk, IterState st) {
-    __shared__ double lds[3 * kT / 64];
+// Multi-shift bookkeeping of column c, run by one whole work-group once
+// r^T r and ||r||^2 of the new residual are known (valid in thread 0).
+__device__ void ms_bookkeeping(int c, double rr_x, double rr_y, double nn, IterState& st) {
     __shared__ double2 sh_sc[6];
     __shared__ int sh_all;
-    const int c = blockIdx.x;
-    if (st.done[c]) return;
-    double s[3] = {0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nblk; b += kT) {
-        const double2 v = part_rr[(int64_t)c * nblk + b];
-        s[0] += v.x;
-        s[1] += v.y;
-        s[2] += part_nn[(int64_t)c * nblk + b];
-    }
-    block_sum<3>(s, lds);
     const int k = st.k[c];
     if (threadIdx.x == 0) {
-        const double2 rho_new = make_double2(s[0], s[1]);
-        const double snew = sqrt(s[2]);
+        const double2 rho_new = make_double2(rr_x, rr_y);
+        const double snew = sqrt(nn);
         const double2 a = st.alpha[c];
         const double2 bprev = st.beta[c];
         const double2 aprev = (k > 0) ? st.a_hist[(int64_t)c * st.max_iter + k - 1] : make_double2(1.0, 0.0);
@@ -233,7 +222,7 @@ __global__ __launch_bounds__(kT) void k_reduce_beta_ms(const double2* __restrict
     const double s0_over_sk = sh_sc[5].x;
     double2* rec = st.rec + ((int64_t)c * st.chunk + k % st.chunk) * 3 * st.ng;
     int all = 1;
-    for (int g = threadIdx.x; g < st.ng; g += kT) {
+    for (int g = threadIdx.x; g < st.ng; g += blockDim.x) {
         const int64_t o = (int64_t)c * st.ng + g;
         // A shift whose residual met tol is frozen: its iterate stays the
         // converged one, and shifts far from the seed would otherwise keep
@@ -276,6 +265,151 @@ __global__ __launch_bounds__(kT) void k_reduce_beta_ms(const double2* __restrict
         } else if (k + 1 >= st.max_iter) {
             st.done[c] = 1 + NEGF_ITEM_MAX_ITER;
         }
+    }
+}
+
+// Multi-shift bookkeeping for one column per work-group (see ms_bookkeeping).
+__global__ __launch_bounds__(kT) void k_reduce_beta_ms(const double2* __restrict__ part_rr,
+                                                       const double* __restrict__ part_nn,
+                                                       int nblk, IterState st) {
+    __shared__ double lds[3 * kT / 64];
+    const int c = blockIdx.x;
+    if (st.done[c]) return;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += kT) {
+        const double2 v = part_rr[(int64_t)c * nblk + b];
+        s[0] += v.x;
+        s[1] += v.y;
+        s[2] += part_nn[(int64_t)c * nblk + b];
+    }
+    block_sum<3>(s, lds);
+    ms_bookkeeping(c, s[0], s[1], s[2], st);
+}
+
+// The residual update of a multi-shift COCG iteration, after the fused
+// stencil kernel (p_k, q_loc = A_loc p_k, p^T q_loc partials) and the
+// projector gather (c = B^T p_k):
+//   alpha_k = rho_k / (p^T q_loc - sum_p E_p c_p^2)   (every work-group, same order)
+//   r_{k+1} = r_k - alpha_k (q_loc - sum_p E_p c_p b_p)   (projector term applied here)
+//   r_{k+1} on the kept rows -> ring slot k+1;  partials of r^T r and ||r||^2.
+// The bookkeeping (beta and the shifts) stays a launch of its own: a
+// last-work-group ticket would need a device-scope release and acquire in
+// every work-group, which on a chip with one L2 per XCD means an L2
+// write-back and invalidate each, far dearer than one small launch.
+template <typename R>
+__global__ __launch_bounds__(kT) void k_update_ms(
+    cplx_t<R>* __restrict__ r, const cplx_t<R>* __restrict__ q, int64_t N, IterState st,
+    const double2* __restrict__ part_f, int nblk_f, const double2* __restrict__ kbc,
+    const double* __restrict__ e_kb, int n_proj, const int* __restrict__ kb_slot,
+    const int* __restrict__ pt_off, const int* __restrict__ pt_proj,
+    const double* __restrict__ pt_val, double2* __restrict__ ring, int ring_len, int w,
+    int64_t row0, int n_rows, double2* __restrict__ part_rr, double* __restrict__ part_nn) {
+    __shared__ double lds[3 * kT / 64];
+    __shared__ double2 sh_alpha;
+    __shared__ int sh_flag;
+    const int c = blockIdx.y;
+    if (st.done[c]) return;
+    const int k = st.k[c];
+    cplx_t<R>* rc = r + (int64_t)c * N;
+    const cplx_t<R>* qc = q + (int64_t)c * N;
+    // each work-group owns one contiguous stretch; U loads per lane in flight
+    constexpr int U = 4;
+    const int64_t span = ((N + gridDim.x - 1) / gridDim.x + kT * U - 1) / (kT * U) * (kT * U);
+    const int64_t i0 = (int64_t)blockIdx.x * span;
+    const int64_t i1 = (i0 + span < N) ? i0 + span : N;
+    cplx_t<R> qv[U], rv[U];
+    auto load = [&](int64_t base) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = base + (int64_t)u * kT;
+            if (i < i1) {
+                qv[u] = qc[i];
+                rv[u] = rc[i];
+            }
+        }
+    };
+    // the first stretch is in flight while alpha is reduced
+    int64_t base = i0 + threadIdx.x;
+    load(base);
+    {
+        double s[2] = {0.0, 0.0};
+        for (int b = threadIdx.x; b < nblk_f; b += kT) {
+            const double2 v = part_f[(int64_t)c * nblk_f + b];
+            s[0] += v.x;
+            s[1] += v.y;
+        }
+        for (int qq = threadIdx.x; qq < n_proj; qq += kT) {
+            const double2 cv = kbc[(int64_t)c * n_proj + qq];
+            const double2 c2 = cmul(cv, cv);
+            s[0] -= e_kb[qq] * c2.x;
+            s[1] -= e_kb[qq] * c2.y;
+        }
+        block_sum<2>(s, lds);
+        if (threadIdx.x == 0) {
+            const double2 mu = make_double2(s[0], s[1]);
+            const double2 a = cdiv(st.rho[c], mu);
+            const bool bad = !cfinite(a) || (mu.x == 0.0 && mu.y == 0.0);
+            sh_alpha = a;
+            sh_flag = bad ? 1 : 0;
+            if (blockIdx.x == 0) {
+                if (bad) {
+                    st.done[c] = 1 + NEGF_ITEM_BREAKDOWN;
+                } else {
+                    st.alpha[c] = a;
+                    st.a_hist[(int64_t)c * st.max_iter + k] = a;
+                }
+            }
+        }
+        __syncthreads();
+        if (sh_flag) return;
+    }
+    const double2 a = sh_alpha;
+    const R ax = (R)a.x, ay = (R)a.y;
+    double2* dst = ring ? ring + ((int64_t)((k + 1) % ring_len) * w + c) * n_rows : nullptr;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (; base < i1; base += kT * U) {
+        cplx_t<R> qn[U], rn[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            qn[u] = qv[u];
+            rn[u] = rv[u];
+        }
+        if (base + kT * U < i1) load(base + kT * U);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = base + (int64_t)u * kT;
+            if (i >= i1) continue;
+            if (kb_slot) {
+                const int sl = kb_slot[i];
+                if (sl >= 0) {
+                    double kx = 0.0, ky = 0.0;
+                    for (int e = pt_off[sl]; e < pt_off[sl + 1]; ++e) {
+                        const double2 cv = kbc[(int64_t)c * n_proj + pt_proj[e]];
+                        kx += pt_val[e] * cv.x;
+                        ky += pt_val[e] * cv.y;
+                    }
+                    qn[u].x -= (R)kx;
+                    qn[u].y -= (R)ky;
+                }
+            }
+            cplx_t<R> v = rn[u];
+            v.x -= ax * qn[u].x - ay * qn[u].y;
+            v.y -= ax * qn[u].y + ay * qn[u].x;
+            rc[i] = v;
+            if (dst) {
+                const int64_t ir = i - row0;
+                if (ir >= 0 && ir < n_rows) dst[ir] = to_d2<R>(v);
+            }
+            const double rx = v.x, ry = v.y;
+            s[0] += rx * rx - ry * ry;
+            s[1] += 2.0 * rx * ry;
+            s[2] += rx * rx + ry * ry;
+        }
+    }
+    block_sum<3>(s, lds);
+    if (threadIdx.x == 0) {
+        part_rr[(int64_t)c * gridDim.x + blockIdx.x] = make_double2(s[0], s[1]);
+        part_nn[(int64_t)c * gridDim.x + blockIdx.x] = s[2];
     }
 }
 
@@ -643,3 +777,21 @@ void launch_weighted_norm(const double2* x64, int64_t N, int w, int64_t row0, in
 INST2(double)
 INST2(float)
 #undef INST2
+
+template <typename R>
+void launch_update_ms(cplx_t<R>* r, const cplx_t<R>* q, int64_t N, const IterState& st,
+                      const double2* part_f, int nblk_f, const negf_op* op, const double2* kbc,
+                      double2* ring, int ring_len, int64_t row0, int n_rows, double2* part_rr,
+                      double* part_nn, hipStream_t s) {
+    dim3 g(part_blocks(N), st.w);
+    const DeviceKB& kb = op->kb;
+    const bool has_kb = kb.n_proj > 0;
+    hipLaunchKernelGGL((k_update_ms<R>), g, dim3(kT), 0, s, r, q, N, st, part_f, nblk_f,
+                       has_kb ? kbc : nullptr, kb.e, kb.n_proj, has_kb ? kb.slot : nullptr,
+                       kb.pt_off, kb.pt_proj, kb.pt_val, ring, ring_len, st.w, row0, n_rows, part_rr,
+                       part_nn);
+}
+template void launch_update_ms<double>(double2*, const double2*, int64_t, const IterState&,
+                                       const double2*, int, const negf_op*, const double2*,
+                                       double2*, int, int64_t, int, double2*, double*,
+                                       hipStream_t);

@@ -185,7 +185,7 @@ static void free_op(negf_op* op) {
     }
     (void)hipSetDevice(op->device);
     void* ptrs[] = {op->d_v, op->d_wz, op->d_wl, op->d_wr, op->kb.off, op->kb.idx, op->kb.val,
-                    op->kb.valf, op->kb.e, op->kb.pts, op->kb.pt_off, op->kb.pt_proj, op->kb.pt_val};
+                    op->kb.valf, op->kb.e, op->kb.pts, op->kb.pt_off, op->kb.pt_proj, op->kb.pt_val, op->kb.slot};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& b : op->bufs)
@@ -318,6 +318,9 @@ static negf_status build_impl(const negf_grid* g, int32_t R, const double* v, co
         CHK(upload(&op->kb.pt_off, pt_off.data(), pt_off.size()));
         CHK(upload(&op->kb.pt_proj, pt_proj.data(), pt_proj.size()));
         CHK(upload(&op->kb.pt_val, pt_val.data(), pt_val.size()));
+        std::vector<int> slot((size_t)N, -1);
+        for (size_t t = 0; t < pts.size(); ++t) slot[pts[t]] = (int)t;
+        CHK(upload(&op->kb.slot, slot.data(), slot.size()));
     }
     CHK(upload(&op->d_v, v, (size_t)N));
     std::vector<double> wz(g->nz);
@@ -552,6 +555,12 @@ struct ChunkGraph {
     }
 };
 
+// NEGF_NO_FUSED_UPDATE=1 runs the multi-shift iteration tail as separate kernels
+static bool fused_update_disabled() {
+    const char* e = std::getenv("NEGF_NO_FUSED_UPDATE");
+    return e && e[0] == '1';
+}
+
 static bool graphs_enabled() {
     const char* e = getenv("NEGF_NO_GRAPH");
     return !(e && atoi(e) != 0);
@@ -651,6 +660,9 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, c
     double2* xi_a = coef + 2 * n_cxp;
     double2* carry = xi_a + 2 * (size_t)w * ng;
     int* active = (int*)(carry + (size_t)w * ng);
+    // the fused update kernel stores contiguous kept rows; a row list takes the
+    // separate kernels
+    const bool fused_update = (d_rows == nullptr) && !fused_update_disabled();
     IterState st;
     CHK(make_state(op, w, ng, d.max_iter, d.tol, true, &st, ch));
 
@@ -691,7 +703,14 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, c
                 hipEvent_t e0, e1;
                 CHK(tm->next(&e0, &e1));
                 launch_cocg_apply<double>(op, r, pin, pout, q, w, shift, st.done, st.k, st.beta,
-                                          part_f, kbc, s, e0, e1);
+                                          part_f, kbc, s, e0, e1, !fused_update);
+                if (fused_update) {
+                    // alpha, projector term, r update and kept rows in one launch
+                    launch_update_ms<double>(r, q, N, st, part_f, nblk_f, op, kbc, ring, ring_len,
+                                             row0, n_rows, part, part_nn, s);
+                    launch_reduce_beta_multishift(part, part_nn, nblk, st, s);
+                    continue;
+                }
                 launch_reduce_alpha(part_f, nblk_f, st, s, op->kb.n_proj ? kbc : nullptr,
                                     op->kb.e, op->kb.n_proj);
                 launch_r_update<double>(r, q, nullptr, nullptr, part, part_nn, st, N, s);

@@ -56,6 +56,7 @@ struct DeviceKB {
     int n_pts = 0;
     int* pts = nullptr;       // [n_pts]
     int* pt_off = nullptr;    // [n_pts + 1]
+    int* slot = nullptr;      // [N] index into pts, or -1
     int* pt_proj = nullptr;   // [nnz]
     double* pt_val = nullptr; // [nnz]  E_p * b_p(i)
     int max_support = 0;
@@ -155,8 +156,15 @@ template <typename R>
 void launch_cocg_apply(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin,
                        cplx_t<R>* pout, cplx_t<R>* q, int w, const double* shift, const int* skip,
                        const int* kit, const double2* beta, double2* part, double2* d_kbc,
-                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, bool kb_scatter = true);
 int fused_partials(const negf_op* op, int w);
+// multi-shift alpha + projector term + r update + kept-row store in one launch
+// (krylov.hip); ring == null skips the row store
+template <typename R>
+void launch_update_ms(cplx_t<R>* r, const cplx_t<R>* q, int64_t N, const IterState& st,
+                      const double2* part_f, int nblk_f, const negf_op* op, const double2* kbc,
+                      double2* ring, int ring_len, int64_t row0, int n_rows, double2* part_rr,
+                      double* part_nn, hipStream_t s);
 template <typename R>
 void launch_r_update(cplx_t<R>* r, const cplx_t<R>* q, cplx_t<R>* p_or_null, cplx_t<R>* x_or_null,
                      double2* part_rr, double* part_nn, const IterState& st, int64_t N,

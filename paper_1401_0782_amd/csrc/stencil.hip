@@ -760,7 +760,7 @@ template <typename R>
 void launch_cocg_apply(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin,
                        cplx_t<R>* pout, cplx_t<R>* q, int w, const double* shift, const int* skip,
                        const int* kit, const double2* beta, double2* part, double2* d_kbc,
-                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, bool kb_scatter) {
     if (ev0) (void)hipEventRecord(ev0, s);
     switch (op->R) {
         case 1: fused_launch<1, R, true>(op, r, pin, pout, q, w, shift, skip, kit, beta, part, s); break;
@@ -776,17 +776,19 @@ void launch_cocg_apply(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* p
         dim3 g1(kb.n_proj, (w + 3) / 4);
         hipLaunchKernelGGL((k_kb_gather<R>), g1, dim3(kThreads), 0, s, pout, op->N, kb.off, kb.idx,
                            kb.val, kb.n_proj, w, d_kbc, skip);
-        dim3 g2((kb.n_pts + kThreads - 1) / kThreads, w);
-        hipLaunchKernelGGL((k_kb_scatter<R>), g2, dim3(kThreads), 0, s, q, op->N, kb.pts,
-                           kb.pt_off, kb.pt_proj, kb.pt_val, kb.n_pts, kb.n_proj, d_kbc, skip);
+        if (kb_scatter) {
+            dim3 g2((kb.n_pts + kThreads - 1) / kThreads, w);
+            hipLaunchKernelGGL((k_kb_scatter<R>), g2, dim3(kThreads), 0, s, q, op->N, kb.pts,
+                               kb.pt_off, kb.pt_proj, kb.pt_val, kb.n_pts, kb.n_proj, d_kbc, skip);
+        }
     }
 }
 
 template void launch_cocg_apply<double>(const negf_op*, const double2*, const double2*, double2*,
                                         double2*, int, const double*, const int*, const int*,
                                         const double2*, double2*, double2*, hipStream_t,
-                                        hipEvent_t, hipEvent_t);
+                                        hipEvent_t, hipEvent_t, bool);
 template void launch_cocg_apply<float>(const negf_op*, const float2*, const float2*, float2*,
                                        float2*, int, const double*, const int*, const int*,
                                        const double2*, double2*, double2*, hipStream_t,
-                                       hipEvent_t, hipEvent_t);
+                                       hipEvent_t, hipEvent_t, bool);
