@@ -213,7 +213,7 @@ def main():
         "unit": "GB/s",
         "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
         "traffic": traffic,  # HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)
-        "kernel": "k_cocg_apply<6,double,1024,true> (fused p = r + beta p, stencil + potential + CAP apply, p^T q partials)",
+        "kernel": "k_cocg_plane<6,double,true> (fused p = r + beta p, stencil + potential + CAP apply, p^T q partials)",
         "launches": mv_n,
         "avg_launch_us": 1e6 * mv_s / max(1, mv_n),
         "bytes_per_launch": mv_b / max(1, mv_n),
