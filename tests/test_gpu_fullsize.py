@@ -78,4 +78,9 @@ def test_oracle_samples(op2, wire2):
                                    col_count=64, block_width=64, tol=1e-11)
         for smp in smps:
             t = d.t_col[smp["e_index"], smp["col"] - 64 * blk]
-            assert abs(t - smp["t_col"]) <= 1e-8 * max(1.0, abs(smp["t_col"])), (smp, t)
+            # |dT| <= 1e-8 on T(E) = sum of 16,384 column terms: each column's
+            # share of that budget is 1e-8 / 16384 ~ 6e-13
+            err = abs(t - smp["t_col"])
+            print(f"col {smp['col']} E {smp['energy']:.4f}: t {t:.6e} oracle {smp['t_col']:.6e} "
+                  f"|dt| {err:.2e}", flush=True)
+            assert err <= 6e-13, (smp, t)
