@@ -170,6 +170,13 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
 
+    # launch shape (z-chunking, stencil kernel) for this block width, picked once
+    # by the library's autotuner before any timing
+    tuned = P.negf_tune(op, wire.energies, block_width=args.block)
+    print(f"tuned launch shape: block {tuned['block_width']}, stencil work-groups "
+          f"{tuned['wg_target']}, whole-plane kernel {tuned['plane_kernel']}",
+          file=sys.stderr, flush=True)
+
     def step(i):
         c0 = (i * args.block) % n_src
         T, d = P.negf_transmission(op, wire.energies, n_cols=args.block, check=False,
@@ -238,6 +245,7 @@ def main():
                          f"{args.block} source columns x {n_e} energies per step, FP64 multi-shift "
                          f"COCG, tol {TOL:g}"),
             "solves_per_step": args.block * n_e,
+            "launch_shape": {k: tuned[k] for k in ("block_width", "wg_target", "plane_kernel")},
             "column_iterations": iters,
             "not_converged": not_conv,
         },

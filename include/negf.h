@@ -191,6 +191,47 @@ negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* ops, const ne
                                     const int32_t* n_e, const double* const* energies,
                                     double* const* T, int32_t* status, int32_t max_concurrent);
 
+/* Launch-shape autotuner for the multi-shift core (the batching form's
+ * tuned block width, z-chunking and stencil kernel).  It times a short run of
+ * probe_iters COCG iterations (0 -> 128: one chunk, so one blocked shift
+ * accumulation is included) of the op's first source columns at the given
+ * energies for every candidate, on the op's stream, and keeps the candidate
+ * with the least device time per column-iteration in the op.  Later
+ * negf_transmission / negf_solve_columns calls on this op whose
+ * opts->block_width is 0 use the tuned width; the z-chunking and kernel choice
+ * apply to every later stencil launch on this op.
+ * Candidates: block width 16, 32, 64, 128 (capped at the source column count;
+ * only opts->block_width when that is nonzero) x stencil work-group targets
+ * 128, 256, 512, 1024 per launch x {whole-plane kernel, row-tiled kernel}
+ * (the whole-plane kernel only where one plane fits a work-group).
+ * Results are identical up to rounding for every candidate: only the launch
+ * shape changes.  Probes that hit max_iter are expected and not errors.
+ *   opts      direction, shift_group, block_width and stream are read
+ *   result    nullable; receives the choice and the timing table */
+#define NEGF_TUNE_MAX 32
+typedef struct {
+    int32_t block_width;  /* chosen source columns per block */
+    int32_t wg_target;    /* chosen stencil work-groups per launch (z-chunking) */
+    int32_t plane_kernel; /* 1 whole-plane stencil kernel, 0 row-tiled */
+    int32_t n_tried;
+    int32_t tried_block_width[NEGF_TUNE_MAX];
+    int32_t tried_wg_target[NEGF_TUNE_MAX];
+    int32_t tried_plane_kernel[NEGF_TUNE_MAX];
+    double us_per_column_iteration[NEGF_TUNE_MAX];
+} negf_tune_result;
+
+negf_status negf_tune(negf_op* op, const negf_opts* opts, int32_t n_e, const double* energies,
+                      int32_t probe_iters, negf_tune_result* result);
+
+/* Sets the launch shape negf_tune would keep, e.g. one cached from an earlier
+ * process: block_width 0 and wg_target 0 restore the built-in defaults (64
+ * columns; 256 stencil work-groups per launch), plane_kernel -1 the automatic
+ * kernel choice.  block_width in [0, 4096], wg_target in [0, 65536],
+ * plane_kernel in {-1, 0, 1}; a whole-plane request on a grid whose plane does
+ * not fit one work-group falls back to the row-tiled kernel. */
+negf_status negf_set_launch_shape(negf_op* op, int32_t block_width, int32_t wg_target,
+                                  int32_t plane_kernel);
+
 /* Adjoint gradient of L = sum_e weights[e] T(E_e) with respect to the local
  * potential: dL_dV[r] = sum_e w_e 8 Re sum_{j in R} W_R,j lambda_j(r) g_j(r),
  * with g_j = A^-1 e_j and lambda_j = A^-1 (W_L o conj(g_j)) solved with the

@@ -22,6 +22,8 @@ from .api import (  # noqa: F401
     negf_transmission,
     negf_transmission_batch,
     negf_transmission_grad,
+    negf_set_launch_shape,
+    negf_tune,
     negf_version,
     operator_from_wire,
 )

@@ -28,6 +28,8 @@ EXPORTS = (
     "negf_solve_columns",
     "negf_transmission",
     "negf_transmission_batch",
+    "negf_tune",
+    "negf_set_launch_shape",
     "negf_transmission_grad",
     "negf_destroy",
     "negf_last_error",
@@ -61,6 +63,18 @@ class negf_diag(C.Structure):
                 ("matvec_bytes", C.c_double)]
 
 
+NEGF_TUNE_MAX = 32
+
+
+class negf_tune_result(C.Structure):
+    _fields_ = [("block_width", C.c_int32), ("wg_target", C.c_int32),
+                ("plane_kernel", C.c_int32), ("n_tried", C.c_int32),
+                ("tried_block_width", C.c_int32 * NEGF_TUNE_MAX),
+                ("tried_wg_target", C.c_int32 * NEGF_TUNE_MAX),
+                ("tried_plane_kernel", C.c_int32 * NEGF_TUNE_MAX),
+                ("us_per_column_iteration", C.c_double * NEGF_TUNE_MAX)]
+
+
 _lib = None
 
 
@@ -86,12 +100,16 @@ def load(path: str | None = None):
     lib.negf_transmission_grad.argtypes = [vp, C.POINTER(negf_opts), C.c_int32, vp, vp, vp, vp]
     lib.negf_transmission_batch.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(negf_opts),
                                             vp, C.POINTER(vp), C.POINTER(vp), vp, C.c_int32]
+    lib.negf_tune.argtypes = [vp, C.POINTER(negf_opts), C.c_int32, vp, C.c_int32,
+                              C.POINTER(negf_tune_result)]
+    lib.negf_set_launch_shape.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
     lib.negf_destroy.argtypes = [vp]
     lib.negf_destroy.restype = None
     lib.negf_last_error.restype = C.c_char_p
     lib.negf_version.restype = C.c_char_p
     for name in ("negf_build_operator", "negf_apply_operator", "negf_solve_columns",
-                 "negf_transmission", "negf_transmission_grad", "negf_transmission_batch"):
+                 "negf_transmission", "negf_transmission_grad", "negf_transmission_batch",
+                 "negf_tune", "negf_set_launch_shape"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

@@ -228,6 +228,32 @@ def negf_transmission_grad(op: Operator, energies, weights, dL_dV=None, want_T=T
     return dL_dV, T
 
 
+def negf_tune(op: Operator, energies, probe_iters: int = 0, **opts) -> dict:
+    """Autotune the multi-shift launch shape of op (block width, stencil
+    z-chunking, stencil kernel) by timing short probe runs; later calls with
+    block_width=0 use the choice.  Returns the choice and the timing table."""
+    e = np.ascontiguousarray(energies, dtype=np.float64)
+    o = _opts(**opts)
+    res = _abi.negf_tune_result()
+    _check(_lib().negf_tune(op.handle, C.byref(o), e.size, _ptr(e), int(probe_iters),
+                            C.byref(res)))
+    n = res.n_tried
+    return {
+        "block_width": res.block_width,
+        "wg_target": res.wg_target,
+        "plane_kernel": res.plane_kernel,
+        "tried": [(res.tried_block_width[i], res.tried_wg_target[i], res.tried_plane_kernel[i],
+                   res.us_per_column_iteration[i]) for i in range(n)],
+    }
+
+
+def negf_set_launch_shape(op: Operator, block_width: int = 0, wg_target: int = 0,
+                          plane_kernel: int = -1) -> None:
+    """Set op's multi-shift launch shape (e.g. a cached negf_tune choice)."""
+    _check(_lib().negf_set_launch_shape(op.handle, int(block_width), int(wg_target),
+                                        int(plane_kernel)))
+
+
 def negf_transmission_batch(ops, energies_list, max_concurrent=0, check=True, **opts):
     """T(E) for many junctions at once; returns (list of T arrays, statuses)."""
     n = len(ops)

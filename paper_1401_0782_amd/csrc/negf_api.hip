@@ -1030,7 +1030,7 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
     int64_t total_iters = 0;
     if (core == NEGF_CORE_MULTISHIFT) {
         const int ng_max = d.shift_group ? std::min(d.shift_group, n_e) : n_e;
-        const int wmax = d.block_width ? d.block_width : 64;
+        const int wmax = d.block_width ? d.block_width : (op->tuned_w ? op->tuned_w : 64);
         std::vector<double> blk_t, blk_r;
         std::vector<int> blk_it, blk_st, blk_si;
         for (int g0 = 0; g0 < n_e; g0 += ng_max) {
@@ -1212,7 +1212,7 @@ static negf_status solve_columns_impl(negf_op* op, const negf_opts* opts, int32_
     int64_t total_iters = 0;
     if (core == NEGF_CORE_MULTISHIFT) {
         const int ng_max = d.shift_group ? std::min(d.shift_group, n_e) : n_e;
-        const int wmax = d.block_width ? d.block_width : 64;
+        const int wmax = d.block_width ? d.block_width : (op->tuned_w ? op->tuned_w : 64);
         std::vector<int> blk_st;
         std::vector<double> blk_r;
         for (int g0 = 0; g0 < n_e; g0 += ng_max) {
@@ -1391,6 +1391,7 @@ extern "C" negf_status negf_transmission_grad(negf_op* op, const negf_opts* opts
 // ---------------------------------------------------------------------------
 // negf_transmission_batch
 // ---------------------------------------------------------------------------
+
 static void release_workspace(negf_op* op) {
     (void)hipStreamSynchronize(op->own_stream);
     for (auto& b : op->bufs) {
@@ -1398,6 +1399,127 @@ static void release_workspace(negf_op* op) {
         b.ptr = nullptr;
         b.bytes = 0;
     }
+}
+
+// ---------------------------------------------------------------------------
+// negf_tune: pick the multi-shift launch shape by timing short probe runs
+// ---------------------------------------------------------------------------
+static negf_status tune_impl(negf_op* op, const negf_opts* opts, int32_t n_e,
+                             const double* energies, int32_t probe_iters,
+                             negf_tune_result* result) {
+    Defaults d;
+    CHK(read_opts(opts, &d));
+    CHK(check_energies(n_e, energies));
+    if (probe_iters < 0) {
+        set_error("probe_iters must be >= 0");
+        return NEGF_E_INVALID_ARG;
+    }
+    HIPCHK(hipSetDevice(op->device));
+    hipStream_t s = pick_stream(op, opts);
+    Sides sd;
+    make_sides(op, d.direction, &sd);
+    const int n_cols = (int)sd.cols.size();
+    const int ng = d.shift_group ? std::min(d.shift_group, n_e) : n_e;
+    Defaults dp = d;
+    dp.max_iter = probe_iters ? probe_iters : kShiftChunk;
+
+    std::vector<int> widths;
+    if (d.block_width) {
+        widths.push_back(std::min(d.block_width, n_cols));
+    } else {
+        for (int w : {16, 32, 64, 128})
+            if (w <= n_cols) widths.push_back(w);
+        if (widths.empty()) widths.push_back(n_cols);
+    }
+    const int pts = op->nx * op->ny;
+    const bool plane_ok = pts <= 1024 && pts % 64 == 0;
+    std::vector<int> kernels = plane_ok ? std::vector<int>{1, 0} : std::vector<int>{0};
+    struct Cand { int w, target, plane; double us; };
+    std::vector<Cand> cands;
+    for (int w : widths)
+        for (int k : kernels)
+            for (int t : {128, 256, 512, 1024}) cands.push_back({w, t, k, 0.0});
+    if ((int)cands.size() > NEGF_TUNE_MAX) cands.resize(NEGF_TUNE_MAX);
+
+    double* d_roww = nullptr;
+    CHK(ws(op, WS_ROWW, (size_t)sd.n_rows, &d_roww));
+    HIPCHK(hipMemcpyAsync(d_roww, sd.roww.data(), sd.n_rows * sizeof(double), hipMemcpyHostToDevice, s));
+    MatvecTimer tm;
+    CHK(tm.init(false));
+    const int saved_w = op->tuned_w, saved_t = op->wg_target, saved_k = op->plane_kernel;
+    auto probe = [&](const Cand& c, double* us) -> negf_status {
+        op->wg_target = c.target;
+        op->plane_kernel = c.plane;
+        MSOut mo;  // nothing copied out
+        int64_t total = 0;
+        HIPCHK(hipStreamSynchronize(s));
+        const auto t0 = std::chrono::steady_clock::now();
+        CHK(run_multishift_block(op, dp, c.w, sd.cols.data(), nullptr, energies, ng, nullptr,
+                                 sd.row0, sd.n_rows, d_roww, sd.colw.data(), mo, &total, s, &tm));
+        HIPCHK(hipStreamSynchronize(s));
+        const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *us = 1e6 * sec / (double)std::max<int64_t>(1, total);
+        return NEGF_OK;
+    };
+    negf_status st = NEGF_OK;
+    double warm = 0.0;
+    st = probe(cands[0], &warm);  // first use allocates the workspace and loads code
+    for (size_t i = 0; st == NEGF_OK && i < cands.size(); ++i) st = probe(cands[i], &cands[i].us);
+    if (st != NEGF_OK) {
+        op->tuned_w = saved_w;
+        op->wg_target = saved_t;
+        op->plane_kernel = saved_k;
+        return st;
+    }
+    size_t best = 0;
+    for (size_t i = 1; i < cands.size(); ++i)
+        if (cands[i].us < cands[best].us) best = i;
+    op->tuned_w = cands[best].w;
+    op->wg_target = cands[best].target;
+    op->plane_kernel = cands[best].plane;
+    release_workspace(op);  // the probes sized it for the widest candidate
+    if (result) {
+        result->block_width = cands[best].w;
+        result->wg_target = cands[best].target;
+        result->plane_kernel = cands[best].plane;
+        result->n_tried = (int32_t)cands.size();
+        for (size_t i = 0; i < cands.size(); ++i) {
+            result->tried_block_width[i] = cands[i].w;
+            result->tried_wg_target[i] = cands[i].target;
+            result->tried_plane_kernel[i] = cands[i].plane;
+            result->us_per_column_iteration[i] = cands[i].us;
+        }
+    }
+    return NEGF_OK;
+}
+
+extern "C" negf_status negf_tune(negf_op* op, const negf_opts* opts, int32_t n_e,
+                                 const double* energies, int32_t probe_iters,
+                                 negf_tune_result* result) {
+    (void)hipGetLastError();  // a stale error of an earlier call must not fail this one
+    if (!op) {
+        set_error("null op");
+        return NEGF_E_INVALID_ARG;
+    }
+    return tune_impl(op, opts, n_e, energies, probe_iters, result);
+}
+
+extern "C" negf_status negf_set_launch_shape(negf_op* op, int32_t block_width, int32_t wg_target,
+                                             int32_t plane_kernel) {
+    if (!op) {
+        set_error("null op");
+        return NEGF_E_INVALID_ARG;
+    }
+    if (block_width < 0 || block_width > 4096 || wg_target < 0 || wg_target > 65536 ||
+        plane_kernel < -1 || plane_kernel > 1) {
+        set_error("launch shape out of range (block_width %d, wg_target %d, plane_kernel %d)",
+                  block_width, wg_target, plane_kernel);
+        return NEGF_E_INVALID_ARG;
+    }
+    op->tuned_w = block_width;
+    op->wg_target = wg_target;
+    op->plane_kernel = plane_kernel;
+    return NEGF_OK;
 }
 
 extern "C" negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* ops,

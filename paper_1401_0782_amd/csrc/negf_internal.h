@@ -83,6 +83,10 @@ struct negf_op {
     DeviceKB kb;
     hipStream_t own_stream = nullptr;
     std::vector<Buffer> bufs;    // workspace, indexed by WorkSlot
+    // launch shape (negf_tune); 0 / -1 = built-in choice
+    int tuned_w = 0;             // source columns per multi-shift block
+    int wg_target = 0;           // stencil work-groups per launch the z-chunking aims for
+    int plane_kernel = -1;       // 1 whole-plane kernel, 0 row-tiled, -1 auto
 };
 
 // status plumbing (thread-local message)

@@ -667,7 +667,8 @@ FusedGeom fused_geom(const negf_op* op, int w) {
     FusedGeom g;
     const int nx = op->nx, ny = op->ny, nz = op->nz;
     const int pts = nx * ny;
-    g.whole_plane = pts <= 1024 && pts % 64 == 0 && getenv("NEGF_NO_PLANE_KERNEL") == nullptr;
+    g.whole_plane = pts <= 1024 && pts % 64 == 0 && op->plane_kernel != 0 &&
+                    getenv("NEGF_NO_PLANE_KERNEL") == nullptr;
     if (g.whole_plane) {
         g.nt = pts;
         g.ty = ny;
@@ -675,7 +676,8 @@ FusedGeom fused_geom(const negf_op* op, int w) {
         // z-chunks: enough work-groups for every CU, each a multiple of the
         // 2R+1 unrolled steps (the last trip of a chunk runs whole)
         constexpr int Q = 2 * RAD + 1;
-        int nzc = std::max(1, (256 + w - 1) / w);
+        const int target = op->wg_target > 0 ? op->wg_target : 256;
+        int nzc = std::max(1, (target + w - 1) / w);
         int zc = (nz + nzc - 1) / nzc;
         zc = std::max(Q, ((zc + Q - 1) / Q) * Q);
         g.zchunk = zc;
@@ -687,7 +689,7 @@ FusedGeom fused_geom(const negf_op* op, int w) {
     g.ty = std::min(ny, g.nt / nx);
     g.n_ytiles = (ny + g.ty - 1) / g.ty;
     // enough work-groups to give every CU work; each z-chunk re-reads 2R planes
-    const long target = (g.nt == 1024) ? 256 : 1024;
+    const long target = op->wg_target > 0 ? op->wg_target : ((g.nt == 1024) ? 256 : 1024);
     int zc = nz;
     while ((long)g.n_ytiles * w * ((nz + zc - 1) / zc) < target && zc > 8 * RAD) zc = (zc + 1) / 2;
     g.zchunk = zc;

@@ -95,3 +95,34 @@ def test_null_output_rejected():
     assert lib.negf_build_operator(C.byref(g), 2, None, None, None, None, None) == _abi.NEGF_E_INVALID_ARG
     assert b"null" in lib.negf_last_error()
     lib.negf_destroy(None)  # no-op
+
+
+def test_tune_rejects_null_operator():
+    from paper_1401_0782_amd import _abi
+
+    lib = _abi.load()
+    e = np.array([0.3])
+    assert lib.negf_tune(None, None, 1, e.ctypes.data, 0, None) == _abi.NEGF_E_INVALID_ARG
+    assert b"null op" in lib.negf_last_error()
+
+
+def test_tune_result_layout_matches_header():
+    """The ctypes mirror of negf_tune_result has the header's field order and size."""
+    from paper_1401_0782_amd import _abi
+
+    text = (ROOT / "include" / "negf.h").read_text()
+    body = re.search(r"typedef struct \{((?:(?!typedef).)*?)\} negf_tune_result;", text, re.S).group(1)
+    fields = re.findall(r"\b(int32_t|double)\s+([a-z_]+)(\[NEGF_TUNE_MAX\])?;", body)
+    assert [f[1] for f in fields] == [f[0] for f in _abi.negf_tune_result._fields_]
+    n_max = int(re.search(r"#define NEGF_TUNE_MAX (\d+)", text).group(1))
+    assert n_max == _abi.NEGF_TUNE_MAX
+    size = sum((4 if t == "int32_t" else 8) * (n_max if arr else 1) for t, _, arr in fields)
+    assert C.sizeof(_abi.negf_tune_result) == size
+
+
+def test_set_launch_shape_validates_without_device():
+    from paper_1401_0782_amd import _abi
+
+    lib = _abi.load()
+    assert lib.negf_set_launch_shape(None, 64, 256, 1) == _abi.NEGF_E_INVALID_ARG
+    assert b"null op" in lib.negf_last_error()
