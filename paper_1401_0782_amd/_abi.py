@@ -63,7 +63,7 @@ class negf_diag(C.Structure):
                 ("matvec_bytes", C.c_double)]
 
 
-NEGF_TUNE_MAX = 32
+NEGF_TUNE_MAX = 40
 
 
 class negf_tune_result(C.Structure):

@@ -455,9 +455,10 @@ __global__ __launch_bounds__(kT) void k_store_rows(const cplx_t<R>* __restrict__
                                                    int n_rows, double2* __restrict__ ring,
                                                    int ring_len, int w,
                                                    const int* __restrict__ done,
-                                                   const int* __restrict__ kit, int slot_offset) {
+                                                   const int* __restrict__ kit, int slot_offset,
+                                                   const int* __restrict__ only) {
     const int c = blockIdx.y;
-    if (done[c]) return;
+    if (done[c] || (only && !only[c])) return;
     const int slot = (kit[c] + slot_offset) % ring_len;
     double2* dst = ring + ((int64_t)slot * w + c) * n_rows;
     const cplx_t<R>* rc = r + (int64_t)c * N;
@@ -522,12 +523,12 @@ void launch_reduce_beta_single(const double2* part_rr, const double* part_nn, in
 template <typename R>
 void launch_store_rows(const cplx_t<R>* r, int64_t N, int w, const int* rows, int64_t row0,
                        int n_rows, double2* ring, int ring_len, const IterState& st,
-                       int slot_offset, hipStream_t s) {
+                       int slot_offset, hipStream_t s, const int* only) {
     int gx = (n_rows + kT - 1) / kT;
     if (gx > 256) gx = 256;
     dim3 g(gx, w);
     hipLaunchKernelGGL((k_store_rows<R>), g, dim3(kT), 0, s, r, N, rows, row0, n_rows, ring,
-                       ring_len, w, st.done, st.k, slot_offset);
+                       ring_len, w, st.done, st.k, slot_offset, only);
 }
 
 #define INST(R)                                                                                  \
@@ -538,7 +539,8 @@ void launch_store_rows(const cplx_t<R>* r, int64_t N, int w, const int* rows, in
     template void launch_r_update<R>(cplx_t<R>*, const cplx_t<R>*, cplx_t<R>*, cplx_t<R>*,      \
                                      double2*, double*, const IterState&, int64_t, hipStream_t); \
     template void launch_store_rows<R>(const cplx_t<R>*, int64_t, int, const int*, int64_t, int, \
-                                       double2*, int, const IterState&, int, hipStream_t);
+                                       double2*, int, const IterState&, int, hipStream_t,        \
+                                       const int*);
 INST(double)
 INST(float)
 #undef INST
@@ -551,8 +553,10 @@ namespace {
 // r[c] = e_{cols[c]} (unit right-hand sides); also b64 when given
 template <typename R>
 __global__ __launch_bounds__(kT) void k_init_unit(cplx_t<R>* __restrict__ r, double2* __restrict__ b64,
-                                                  int64_t N, const int* __restrict__ cols) {
+                                                  int64_t N, const int* __restrict__ cols,
+                                                  const int* __restrict__ only) {
     const int c = blockIdx.y;
+    if (only && !only[c]) return;
     const int j = cols[c];
     for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kT) {
         cplx_t<R> v; v.x = (i == j) ? (R)1 : (R)0; v.y = 0;
@@ -589,9 +593,11 @@ __global__ __launch_bounds__(kT) void k_norms(const cplx_t<R>* __restrict__ v, i
 // Columns flagged in skip start (and stay) done.
 __global__ __launch_bounds__(kT) void k_reduce_init(const double2* __restrict__ part_rr,
                                                     const double* __restrict__ part_nn, int nblk,
-                                                    IterState st, const int* __restrict__ skip) {
+                                                    IterState st, const int* __restrict__ skip,
+                                                    const int* __restrict__ only) {
     __shared__ double lds[3 * kT / 64];
     const int c = blockIdx.x;
+    if (only && !only[c]) return;  // column left as it is
     double s[3] = {0.0, 0.0, 0.0};
     const bool sk = skip && skip[c];
     if (!sk) {
@@ -723,9 +729,10 @@ __global__ __launch_bounds__(kT) void k_weighted_norm(const double2* __restrict_
 }  // namespace
 
 template <typename R>
-void launch_init_unit(cplx_t<R>* r, double2* b64, int64_t N, int w, const int* cols, hipStream_t s) {
+void launch_init_unit(cplx_t<R>* r, double2* b64, int64_t N, int w, const int* cols, hipStream_t s,
+                      const int* only) {
     dim3 g(part_blocks(N), w);
-    hipLaunchKernelGGL((k_init_unit<R>), g, dim3(kT), 0, s, r, b64, N, cols);
+    hipLaunchKernelGGL((k_init_unit<R>), g, dim3(kT), 0, s, r, b64, N, cols, only);
 }
 template <typename R>
 void launch_norms(const cplx_t<R>* v, int64_t N, int w, const int* skip, double2* part_rr,
@@ -734,8 +741,9 @@ void launch_norms(const cplx_t<R>* v, int64_t N, int w, const int* skip, double2
     hipLaunchKernelGGL((k_norms<R>), g, dim3(kT), 0, s, v, N, skip, part_rr, part_nn);
 }
 void launch_reduce_init(const double2* part_rr, const double* part_nn, int nblk, IterState st,
-                        const int* skip, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_init, dim3(st.w), dim3(kT), 0, s, part_rr, part_nn, nblk, st, skip);
+                        const int* skip, hipStream_t s, const int* only) {
+    hipLaunchKernelGGL(k_reduce_init, dim3(st.w), dim3(kT), 0, s, part_rr, part_nn, nblk, st, skip,
+                       only);
 }
 void launch_residual(const double2* b, const double2* q, double2* r, int64_t N, int w,
                      const int* skip, double* part, hipStream_t s) {
@@ -767,7 +775,7 @@ void launch_weighted_norm(const double2* x64, int64_t N, int w, int64_t row0, in
 
 #define INST2(R)                                                                                 \
     template void launch_init_unit<R>(cplx_t<R>*, double2*, int64_t, int, const int*,           \
-                                      hipStream_t);                                             \
+                                      hipStream_t, const int*);                                 \
     template void launch_norms<R>(const cplx_t<R>*, int64_t, int, const int*, double2*,        \
                                   double*, hipStream_t);                                        \
     template void launch_scale_convert<R>(const double2*, cplx_t<R>*, cplx_t<R>*, int64_t, int, \

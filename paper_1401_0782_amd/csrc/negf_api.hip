@@ -19,13 +19,15 @@
 
 // launchers defined in krylov.hip (kept out of the shared header because only
 // this file calls them)
+// only (nullable): columns to touch; the others are left as they are
 template <typename R>
-void launch_init_unit(cplx_t<R>* r, double2* b64, int64_t N, int w, const int* cols, hipStream_t s);
+void launch_init_unit(cplx_t<R>* r, double2* b64, int64_t N, int w, const int* cols, hipStream_t s,
+                      const int* only = nullptr);
 template <typename R>
 void launch_norms(const cplx_t<R>* v, int64_t N, int w, const int* skip, double2* part_rr,
                   double* part_nn, hipStream_t s);
 void launch_reduce_init(const double2* part_rr, const double* part_nn, int nblk, IterState st,
-                        const int* skip, hipStream_t s);
+                        const int* skip, hipStream_t s, const int* only = nullptr);
 void launch_residual(const double2* b, const double2* q, double2* r, int64_t N, int w,
                      const int* skip, double* part, hipStream_t s);
 void launch_reduce_residual(const double* part, int nblk, int w, int* odone, const double* bnorm64,
@@ -561,6 +563,12 @@ static bool fused_update_disabled() {
     return e && e[0] == '1';
 }
 
+// NEGF_NO_COLUMN_STREAM=1 runs each block of source columns on its own
+static bool column_stream_disabled() {
+    const char* e = std::getenv("NEGF_NO_COLUMN_STREAM");
+    return e && e[0] == '1';
+}
+
 static bool graphs_enabled() {
     const char* e = getenv("NEGF_NO_GRAPH");
     return !(e && atoi(e) != 0);
@@ -610,31 +618,42 @@ static negf_status run_chunk(ChunkGraph& cg, bool use_graph, hipStream_t s, Matv
 
 // Output of one multi-shift block.
 struct MSOut {
-    double* h_tcol = nullptr;   // [w][ng] host (transmission mode)
-    double2* d_out = nullptr;   // device destination of X (column mode)
+    double* h_tcol = nullptr;   // [n_src][ng] host (transmission mode)
+    double2* d_out = nullptr;   // device destination of X (column mode, n_src == w)
     int64_t out_col_stride = 0, out_shift_stride = 0;
-    int* h_iters = nullptr;     // [w]
-    int* h_status = nullptr;    // [w] column status
-    double* h_resid = nullptr;  // [w][ng] residual estimate per energy
-    int* h_shift_iters = nullptr; // [w][ng] iteration at which each energy converged (0: not)
+    int* h_iters = nullptr;     // [n_src]
+    int* h_status = nullptr;    // [n_src] column status
+    double* h_resid = nullptr;  // [n_src][ng] residual estimate per energy
+    int* h_shift_iters = nullptr; // [n_src][ng] iteration at which each energy converged (0: not)
 };
 
 // iterations per blocked shift update (and per ring half)
 static constexpr int kShiftChunk = 128;
 
-// One block of w columns through the multi-shift core (FP64).
-//   cols (host) unit right-hand sides, or d_rhs (device [w][N]) dense ones
+// The multi-shift core (FP64) on a block of w column slots.
+//   cols (host, n_src entries) unit right-hand sides, or d_rhs (device [w][N])
+//   dense ones (then n_src == w); h_col_w (host, n_src) the T weights
 //   rows kept per energy: contiguous [row0, row0+n_rows) when d_rows == null
-static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, const int* cols,
-                                        const double2* d_rhs, const double* energies, int ng,
-                                        const int* d_rows, int64_t row0, int n_rows,
-                                        const double* d_row_w, const double* h_col_w,
-                                        const MSOut& out, int64_t* total_iters, hipStream_t s,
-                                        MatvecTimer* tm) {
+// With n_src > w (unit right-hand sides, transmission mode) the slots stream
+// through the queue of source columns: at a chunk boundary every slot whose
+// column has finished hands over that column's results and restarts on the
+// next queued column, so the block stays full until the queue runs dry and
+// only the last columns leave slots idle.  Each column's arithmetic is the
+// same as in a block of its own.
+static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, int n_src,
+                                        const int* cols, const double2* d_rhs,
+                                        const double* energies, int ng, const int* d_rows,
+                                        int64_t row0, int n_rows, const double* d_row_w,
+                                        const double* h_col_w, const MSOut& out,
+                                        int64_t* total_iters, hipStream_t s, MatvecTimer* tm) {
     const int64_t N = op->N;
     const int nblk = part_blocks(N);
     const int nblk_f = fused_partials(op, w);
     const int ch = kShiftChunk, ring_len = 2 * kShiftChunk;
+    if (n_src < w || (n_src > w && (!cols || out.d_out))) {
+        set_error("internal: column streaming needs unit right-hand sides in transmission mode");
+        return NEGF_E_INVALID_ARG;
+    }
     double2 *r, *p, *p2, *q, *part, *kbc, *ring, *X, *P, *coef, *part_f;
     double *part_nn, *shift;
     int* d_cols;
@@ -660,11 +679,16 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, c
     double2* xi_a = coef + 2 * n_cxp;
     double2* carry = xi_a + 2 * (size_t)w * ng;
     int* active = (int*)(carry + (size_t)w * ng);
-    // the fused update kernel stores contiguous kept rows; a row list takes the
-    // separate kernels
-    const bool fused_update = (d_rows == nullptr) && !fused_update_disabled();
+    // per slot: iteration count at the chunk start, a slot mask, its T weight
+    int* slots;
+    CHK(ws(op, WS_SLOTS, 3 * (size_t)w, &slots));
+    int* kstart = slots;
+    int* d_mask = slots + w;
+    int* d_notmask = slots + 2 * w;
     IterState st;
     CHK(make_state(op, w, ng, d.max_iter, d.tol, true, &st, ch));
+    // fused update (alpha, projector term, r, kept rows) needs contiguous kept rows
+    const bool fused_update = (d_rows == nullptr) && !fused_update_disabled();
 
     // seed: the highest energy of the group (usually the slowest system)
     double e_seed = energies[0];
@@ -674,8 +698,14 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, c
         for (int g = 0; g < ng; ++g) h_delta[(size_t)c * ng + g] = energies[g] - e_seed;
     HIPCHK(hipMemcpyAsync(shift, h_shift.data(), w * sizeof(double), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(st.deltas, h_delta.data(), h_delta.size() * sizeof(double), hipMemcpyHostToDevice, s));
+
+    // slot -> source column (-1: idle); the first w columns start together
+    std::vector<int> slot_src(w), h_colsel(w, 0), h_mask(w), h_notmask(w);
+    for (int c = 0; c < w; ++c) slot_src[c] = c;
+    int next_src = w;
     if (cols) {
-        HIPCHK(hipMemcpyAsync(d_cols, cols, w * sizeof(int), hipMemcpyHostToDevice, s));
+        for (int c = 0; c < w; ++c) h_colsel[c] = cols[c];
+        HIPCHK(hipMemcpyAsync(d_cols, h_colsel.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
         launch_init_unit<double>(r, nullptr, N, w, d_cols, s);
     } else {
         HIPCHK(hipMemcpyAsync(r, d_rhs, (size_t)w * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
@@ -688,16 +718,28 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, c
     launch_store_rows<double>(r, N, w, d_rows, row0, n_rows, ring, ring_len, st, 0, s);
     HIPCHK(hipGetLastError());
 
-    std::vector<int> h_done(w), h_k(w);
-    int k0 = 0;
+    // per-slot readbacks and the T scratch of finishing slots
+    double *tcol = nullptr, *col_w = nullptr;
+    if (out.h_tcol) {
+        CHK(ws(op, WS_TCOL, (size_t)w * ng + w, &tcol));
+        col_w = tcol + (size_t)w * ng;
+    }
+    std::vector<int> h_done(w), h_k(w), h_si;
+    std::vector<double> h_t, h_res;
+    std::vector<double> h_colw(w, 0.0);
+    int64_t col_iters = 0;
+    int launches = 0;
     ChunkGraph cg;
     const bool use_graph = graphs_enabled();
     while (true) {
-        const int steps = std::min(ch, d.max_iter - k0);
+        // a streaming block runs whole chunks (each column stops at its own
+        // max_iter); a single block stops at max_iter
+        const int steps = (n_src > w) ? ch : std::min(ch, d.max_iter - launches);
+        HIPCHK(hipMemcpyAsync(kstart, st.k, w * sizeof(int), hipMemcpyDeviceToDevice, s));
         auto issue = [&]() -> negf_status {
             for (int it = 0; it < steps; ++it) {
                 // p ping-pongs so that halo reads of the fused kernel see p_{k-1};
-                // chunks start at even k
+                // every column starts at an even k
                 double2* pin = (it & 1) ? p2 : p;
                 double2* pout = (it & 1) ? p : p2;
                 hipEvent_t e0, e1;
@@ -721,44 +763,111 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, c
         };
         CHK(run_chunk(cg, use_graph && steps == ch, s, tm, issue));
         // fold the chunk's iterations into X and P of every energy
-        launch_chunk_coef(st, k0, cx, cp, xi_a, carry, active, s);
-        launch_gemm_xp(ring, ring_len, w, n_rows, k0, st, cx, cp, xi_a, active, X, P, s);
+        launch_chunk_coef(st, kstart, cx, cp, xi_a, carry, active, s);
+        launch_gemm_xp(ring, ring_len, w, n_rows, kstart, st, cx, cp, xi_a, active, X, P, s);
         HIPCHK(hipGetLastError());
-        k0 += steps;
+        launches += steps;
         HIPCHK(hipMemcpyAsync(h_done.data(), st.done, w * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h_k.data(), st.k, w * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         CHK(tm->flush());
-        bool all = true;
-        for (int c = 0; c < w; ++c) all = all && h_done[c] != 0;
-        if (all || k0 >= d.max_iter) break;
+        const bool stop = (n_src == w) && launches >= d.max_iter;
+        // slots whose column is done hand over its results
+        int n_fin = 0;
+        for (int c = 0; c < w; ++c) {
+            h_mask[c] = (slot_src[c] >= 0 && (h_done[c] != 0 || stop)) ? 1 : 0;
+            n_fin += h_mask[c];
+        }
+        if (n_fin > 0 && out.d_out) {
+            // column mode: X stays in place and is copied out at the end
+            for (int c = 0; c < w; ++c)
+                if (h_mask[c]) slot_src[c] = -1;
+        } else if (n_fin > 0) {
+            const bool all_fin = (n_fin == w);
+            HIPCHK(hipMemcpyAsync(d_mask, h_mask.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
+            if (out.h_tcol) {
+                for (int c = 0; c < w; ++c) h_colw[c] = h_mask[c] ? h_col_w[slot_src[c]] : 0.0;
+                HIPCHK(hipMemcpyAsync(col_w, h_colw.data(), w * sizeof(double), hipMemcpyHostToDevice, s));
+                launch_t_from_x(X, n_rows, w, ng, d_row_w, col_w, all_fin ? nullptr : d_mask, tcol, s);
+                h_t.resize((size_t)w * ng);
+                HIPCHK(hipMemcpyAsync(h_t.data(), tcol, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+            }
+            h_res.resize((size_t)w * ng);
+            h_si.resize((size_t)w * ng);
+            HIPCHK(hipMemcpyAsync(h_res.data(), st.sres, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(h_si.data(), st.sconv, (size_t)w * ng * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (int c = 0; c < w; ++c) {
+                if (!h_mask[c]) continue;
+                const int j = slot_src[c];
+                col_iters += h_k[c];
+                *total_iters += h_k[c];
+                if (out.h_iters) out.h_iters[j] = h_k[c];
+                if (out.h_status) out.h_status[j] = h_done[c] ? h_done[c] - 1 : NEGF_ITEM_MAX_ITER;
+                for (int g = 0; g < ng; ++g) {
+                    const size_t so = (size_t)c * ng + g, dof = (size_t)j * ng + g;
+                    if (out.h_tcol) out.h_tcol[dof] = h_t[so];
+                    if (out.h_resid) out.h_resid[dof] = h_res[so];
+                    if (out.h_shift_iters) out.h_shift_iters[dof] = h_si[so];
+                }
+                slot_src[c] = -1;
+            }
+        }
+        // restart finished slots on queued columns
+        int n_new = 0;
+        for (int c = 0; c < w; ++c) {
+            h_mask[c] = 0;
+            if (slot_src[c] < 0 && next_src < n_src && n_src > w) {
+                slot_src[c] = next_src++;
+                h_colsel[c] = cols[slot_src[c]];
+                h_mask[c] = 1;
+                ++n_new;
+            }
+            h_notmask[c] = 1 - h_mask[c];
+        }
+        if (n_new > 0) {
+            HIPCHK(hipMemcpyAsync(d_mask, h_mask.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(d_notmask, h_notmask.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(d_cols, h_colsel.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
+            launch_init_unit<double>(r, nullptr, N, w, d_cols, s, d_mask);
+            for (int c = 0; c < w; ++c) {
+                if (!h_mask[c]) continue;
+                const size_t xo = (size_t)c * ng * n_rows;
+                HIPCHK(hipMemsetAsync(X + xo, 0, (size_t)ng * n_rows * sizeof(double2), s));
+                HIPCHK(hipMemsetAsync(P + xo, 0, (size_t)ng * n_rows * sizeof(double2), s));
+                HIPCHK(hipMemsetAsync(carry + (size_t)c * ng, 0, (size_t)ng * sizeof(double2), s));
+            }
+            launch_norms<double>(r, N, w, d_notmask, part, part_nn, s);
+            launch_reduce_init(part, part_nn, nblk, st, nullptr, s, d_mask);
+            launch_store_rows<double>(r, N, w, d_rows, row0, n_rows, ring, ring_len, st, 0, s, d_mask);
+            HIPCHK(hipGetLastError());
+        }
+        bool busy = false;
+        for (int c = 0; c < w; ++c) busy = busy || slot_src[c] >= 0;
+        if (!busy) break;
     }
-    HIPCHK(hipMemcpyAsync(h_k.data(), st.k, w * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
     if (tm->on) {
         // per column-iteration: r, p_{k-1} read, p_k, q written; V once per launch
-        int64_t col_iters = 0;
-        for (int c = 0; c < w; ++c) col_iters += h_k[c];
-        tm->bytes += 4.0 * sizeof(double2) * (double)N * (double)col_iters + 8.0 * N * k0;
+        tm->bytes += 4.0 * sizeof(double2) * (double)N * (double)col_iters + 8.0 * N * launches;
     }
-    for (int c = 0; c < w; ++c) {
-        *total_iters += h_k[c];
-        if (out.h_iters) out.h_iters[c] = h_k[c];
-        if (out.h_status) out.h_status[c] = h_done[c] ? h_done[c] - 1 : NEGF_ITEM_MAX_ITER;
-    }
-    if (out.h_tcol) {
-        double *tcol, *col_w;
-        CHK(ws(op, WS_TCOL, (size_t)w * ng + w, &tcol));
-        col_w = tcol + (size_t)w * ng;
-        HIPCHK(hipMemcpyAsync(col_w, h_col_w, w * sizeof(double), hipMemcpyHostToDevice, s));
-        launch_t_from_x(X, n_rows, w, ng, d_row_w, col_w, tcol, s);
-        HIPCHK(hipMemcpyAsync(out.h_tcol, tcol, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
-    }
-    if (out.d_out)
+    if (out.d_out) {
+        // column mode: every slot is still live here (n_src == w)
+        for (int c = 0; c < w; ++c) {
+            *total_iters += h_k[c];
+            if (out.h_iters) out.h_iters[c] = h_k[c];
+            if (out.h_status) out.h_status[c] = h_done[c] ? h_done[c] - 1 : NEGF_ITEM_MAX_ITER;
+        }
+        if (tm->on) {
+            int64_t ci = 0;
+            for (int c = 0; c < w; ++c) ci += h_k[c];
+            tm->bytes += 4.0 * sizeof(double2) * (double)N * (double)ci;
+        }
         launch_copy_out(X, n_rows, w, ng, out.d_out, out.out_col_stride, out.out_shift_stride, s);
-    if (out.h_resid)
-        HIPCHK(hipMemcpyAsync(out.h_resid, st.sres, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (out.h_shift_iters)
-        HIPCHK(hipMemcpyAsync(out.h_shift_iters, st.sconv, (size_t)w * ng * sizeof(int), hipMemcpyDeviceToHost, s));
+        if (out.h_resid)
+            HIPCHK(hipMemcpyAsync(out.h_resid, st.sres, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (out.h_shift_iters)
+            HIPCHK(hipMemcpyAsync(out.h_shift_iters, st.sconv, (size_t)w * ng * sizeof(int), hipMemcpyDeviceToHost, s));
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     return NEGF_OK;
@@ -1031,27 +1140,32 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
     if (core == NEGF_CORE_MULTISHIFT) {
         const int ng_max = d.shift_group ? std::min(d.shift_group, n_e) : n_e;
         const int wmax = d.block_width ? d.block_width : (op->tuned_w ? op->tuned_w : 64);
+        // the shard's columns stream through one block of slots; with
+        // NEGF_NO_COLUMN_STREAM=1 each block of wmax columns runs on its own
+        const bool stream = !column_stream_disabled();
         std::vector<double> blk_t, blk_r;
         std::vector<int> blk_it, blk_st, blk_si;
         for (int g0 = 0; g0 < n_e; g0 += ng_max) {
             const int ng = std::min(ng_max, n_e - g0);
-            for (int c0 = 0; c0 < n_cols; c0 += wmax) {
-                const int w = std::min(wmax, n_cols - c0);
-                blk_t.assign((size_t)w * ng, 0.0);
-                blk_r.assign((size_t)w * ng, 0.0);
-                blk_it.assign(w, 0);
-                blk_st.assign(w, 0);
-                blk_si.assign((size_t)w * ng, 0);
+            const int span = stream ? n_cols : wmax;
+            for (int c0 = 0; c0 < n_cols; c0 += span) {
+                const int n_src = std::min(span, n_cols - c0);
+                const int w = std::min(wmax, n_src);
+                blk_t.assign((size_t)n_src * ng, 0.0);
+                blk_r.assign((size_t)n_src * ng, 0.0);
+                blk_it.assign(n_src, 0);
+                blk_st.assign(n_src, 0);
+                blk_si.assign((size_t)n_src * ng, 0);
                 MSOut mo;
                 mo.h_tcol = blk_t.data();
                 mo.h_iters = blk_it.data();
                 mo.h_status = blk_st.data();
                 mo.h_resid = blk_r.data();
                 mo.h_shift_iters = blk_si.data();
-                CHK(run_multishift_block(op, d, w, sd.cols.data() + c0, nullptr, energies + g0, ng,
-                                         nullptr, sd.row0, sd.n_rows, d_roww, sd.colw.data() + c0,
-                                         mo, &total_iters, s, &tm));
-                for (int c = 0; c < w; ++c)
+                CHK(run_multishift_block(op, d, w, n_src, sd.cols.data() + c0, nullptr, energies + g0,
+                                         ng, nullptr, sd.row0, sd.n_rows, d_roww,
+                                         sd.colw.data() + c0, mo, &total_iters, s, &tm));
+                for (int c = 0; c < n_src; ++c)
                     for (int g = 0; g < ng; ++g) {
                         const size_t o = (size_t)(g0 + g) * n_cols + c0 + c;
                         tcol[o] = blk_t[(size_t)c * ng + g];
@@ -1227,7 +1341,7 @@ static negf_status solve_columns_impl(negf_op* op, const negf_opts* opts, int32_
                 mo.out_shift_stride = (int64_t)n_rhs * n_rows;
                 mo.h_status = blk_st.data();
                 mo.h_resid = blk_r.data();
-                CHK(run_multishift_block(op, d, w, rhs_idx ? rhs_idx + c0 : nullptr,
+                CHK(run_multishift_block(op, d, w, w, rhs_idx ? rhs_idx + c0 : nullptr,
                                          d_rhs_all ? d_rhs_all + (size_t)c0 * N : nullptr,
                                          energies + g0, ng, d_rows, 0, n_rows, nullptr, nullptr,
                                          mo, &total_iters, s, &tm));
@@ -1404,6 +1518,17 @@ static void release_workspace(negf_op* op) {
 // ---------------------------------------------------------------------------
 // negf_tune: pick the multi-shift launch shape by timing short probe runs
 // ---------------------------------------------------------------------------
+// device bytes of run_multishift_block's workspace for a block of w columns
+static double multishift_bytes(const negf_op* op, int w, int ng, int n_rows, int max_iter) {
+    const double N = (double)op->N, ch = kShiftChunk, z = sizeof(double2);
+    const double vec = 4.0 * w * N * z;                             // r, p (x2), q
+    const double ring = 2.0 * ch * w * n_rows * z;
+    const double xp = 2.0 * w * (double)ng * n_rows * z;
+    const double coef = (2.0 * ch + 4.0) * w * ng * z;
+    const double state = (double)w * max_iter * (2.0 * z + 8.0) + 3.0 * w * ch * ng * z;
+    return vec + ring + xp + coef + state;
+}
+
 static negf_status tune_impl(negf_op* op, const negf_opts* opts, int32_t n_e,
                              const double* energies, int32_t probe_iters,
                              negf_tune_result* result) {
@@ -1423,13 +1548,21 @@ static negf_status tune_impl(negf_op* op, const negf_opts* opts, int32_t n_e,
     Defaults dp = d;
     dp.max_iter = probe_iters ? probe_iters : kShiftChunk;
 
+    // widths whose multi-shift workspace (at the caller's max_iter) fits in
+    // half of the free device memory
+    size_t mem_free = 0, mem_total = 0;
+    HIPCHK(hipMemGetInfo(&mem_free, &mem_total));
+    auto fits = [&](int w) {
+        const double b = multishift_bytes(op, w, ng, sd.n_rows, d.max_iter);
+        return b <= 0.5 * (double)mem_free;
+    };
     std::vector<int> widths;
     if (d.block_width) {
         widths.push_back(std::min(d.block_width, n_cols));
     } else {
-        for (int w : {16, 32, 64, 128})
-            if (w <= n_cols) widths.push_back(w);
-        if (widths.empty()) widths.push_back(n_cols);
+        for (int w : {16, 32, 64, 128, 256})
+            if (w <= n_cols && fits(w)) widths.push_back(w);
+        if (widths.empty()) widths.push_back(std::min(16, n_cols));
     }
     const int pts = op->nx * op->ny;
     const bool plane_ok = pts <= 1024 && pts % 64 == 0;
@@ -1454,7 +1587,7 @@ static negf_status tune_impl(negf_op* op, const negf_opts* opts, int32_t n_e,
         int64_t total = 0;
         HIPCHK(hipStreamSynchronize(s));
         const auto t0 = std::chrono::steady_clock::now();
-        CHK(run_multishift_block(op, dp, c.w, sd.cols.data(), nullptr, energies, ng, nullptr,
+        CHK(run_multishift_block(op, dp, c.w, c.w, sd.cols.data(), nullptr, energies, ng, nullptr,
                                  sd.row0, sd.n_rows, d_roww, sd.colw.data(), mo, &total, s, &tm));
         HIPCHK(hipStreamSynchronize(s));
         const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

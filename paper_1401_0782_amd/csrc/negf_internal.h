@@ -103,7 +103,7 @@ enum WorkSlot {
     WS_R = 0, WS_P, WS_Q, WS_X, WS_B, WS_R64, WS_X64, WS_Q64,
     WS_PART, WS_PART2, WS_PART3, WS_KBC, WS_SHIFT, WS_COLJ,
     WS_STATE, WS_HIST, WS_PI, WS_GAMMA, WS_TRI, WS_TPART, WS_TCOL, WS_ROWS,
-    WS_ROWW, WS_RING, WS_XS, WS_PS, WS_COEF, WS_MISC, WS_SINK, WS_COUNT
+    WS_ROWW, WS_RING, WS_XS, WS_PS, WS_COEF, WS_MISC, WS_SINK, WS_SLOTS, WS_COUNT
 };
 negf_status ws_get(negf_op* op, int slot, size_t bytes, void** out);
 
@@ -180,15 +180,16 @@ void launch_reduce_beta_single(const double2* part_rr, const double* part_nn, in
 template <typename R>
 void launch_store_rows(const cplx_t<R>* r, int64_t N, int w, const int* rows, int64_t row0,
                        int n_rows, double2* ring, int ring_len, const IterState& st,
-                       int slot_offset, hipStream_t s);
+                       int slot_offset, hipStream_t s, const int* only = nullptr);
 // blocked multi-shift accumulation (shift.hip)
-void launch_chunk_coef(const IterState& st, int k0, double2* cx, double2* cp, double2* xi_a,
-                       double2* carry, int* active, hipStream_t s);
-void launch_gemm_xp(const double2* ring, int ring_len, int w, int n_rows, int k0,
+// kstart[c]: the column's iteration count at the start of the chunk
+void launch_chunk_coef(const IterState& st, const int* kstart, double2* cx, double2* cp,
+                       double2* xi_a, double2* carry, int* active, hipStream_t s);
+void launch_gemm_xp(const double2* ring, int ring_len, int w, int n_rows, const int* kstart,
                     const IterState& st, const double2* cx, const double2* cp,
                     const double2* xi_a, const int* active, double2* X, double2* P,
                     hipStream_t s);
 void launch_t_from_x(const double2* X, int n_rows, int w, int ng, const double* row_w,
-                     const double* col_w, double* t, hipStream_t s);
+                     const double* col_w, const int* only, double* t, hipStream_t s);
 void launch_copy_out(const double2* X, int n_rows, int w, int ng, double2* out, int64_t col_stride,
                      int64_t shift_stride, hipStream_t s);

@@ -24,8 +24,10 @@ namespace {
 
 constexpr int kT = 256;
 
-// One thread per (column, energy): coefficients of the chunk [k0, k0 + cl).
-__global__ __launch_bounds__(kT) void k_chunk_coef(IterState st, int k0, double2* __restrict__ cx,
+// One thread per (column, energy): coefficients of the column's chunk
+// [kstart, kstart + cl) (kstart is a multiple of the chunk length).
+__global__ __launch_bounds__(kT) void k_chunk_coef(IterState st, const int* __restrict__ kstart,
+                                                   double2* __restrict__ cx,
                                                    double2* __restrict__ cp,
                                                    double2* __restrict__ xi_a,
                                                    double2* __restrict__ carry,
@@ -34,7 +36,7 @@ __global__ __launch_bounds__(kT) void k_chunk_coef(IterState st, int k0, double2
     const int c = blockIdx.y;
     const int ng = st.ng, ch = st.chunk;
     if (g >= ng) return;
-    const int cl = max(0, min(ch, st.k[c] - k0));
+    const int cl = max(0, min(ch, st.k[c] - kstart[c]));
     const int64_t o = (int64_t)c * ng + g;
     double2* CX = cx + (int64_t)c * ch * ng + g;
     double2* CP = cp + (int64_t)c * ch * ng + g;
@@ -74,7 +76,8 @@ __global__ __launch_bounds__(kT) void k_chunk_coef(IterState st, int k0, double2
 constexpr int TM = 64, TN = 64, TK = 16;
 
 __global__ __launch_bounds__(kT) void k_gemm_xp(const double2* __restrict__ ring, int ring_len,
-                                                int w, int n_rows, int k0, IterState st,
+                                                int w, int n_rows, const int* __restrict__ kstart,
+                                                IterState st,
                                                 const double2* __restrict__ cx,
                                                 const double2* __restrict__ cp,
                                                 const double2* __restrict__ xi_a,
@@ -88,6 +91,7 @@ __global__ __launch_bounds__(kT) void k_gemm_xp(const double2* __restrict__ ring
     const int row0 = blockIdx.x * TM;
     const int g0 = blockIdx.y * TN;
     const int ng = st.ng, ch = st.chunk;
+    const int k0 = kstart[c];
     const int cl = max(0, min(ch, st.k[c] - k0));
     if (cl == 0) return;
     const int tid = threadIdx.x;
@@ -171,13 +175,16 @@ __global__ __launch_bounds__(kT) void k_gemm_xp(const double2* __restrict__ ring
     }
 }
 
-// t[c][g] = col_w[c] * sum_row row_w[row] |X[c][g][row]|^2, one work-group per (g, c)
+// t[c][g] = col_w[c] * sum_row row_w[row] |X[c][g][row]|^2, one work-group per (g, c);
+// only (nullable) selects the columns to reduce
 __global__ __launch_bounds__(kT) void k_t_from_x(const double2* __restrict__ X, int n_rows, int ng,
                                                  const double* __restrict__ row_w,
                                                  const double* __restrict__ col_w,
+                                                 const int* __restrict__ only,
                                                  double* __restrict__ t) {
     __shared__ double lds[kT / 64];
     const int g = blockIdx.x, c = blockIdx.y;
+    if (only && !only[c]) return;
     const double2* x = X + ((int64_t)c * ng + g) * n_rows;
     double s = 0.0;
     for (int i = threadIdx.x; i < n_rows; i += kT) s += row_w[i] * cabs2(x[i]);
@@ -204,24 +211,25 @@ __global__ __launch_bounds__(kT) void k_copy_out(const double2* __restrict__ X, 
 
 }  // namespace
 
-void launch_chunk_coef(const IterState& st, int k0, double2* cx, double2* cp, double2* xi_a,
-                       double2* carry, int* active, hipStream_t s) {
+void launch_chunk_coef(const IterState& st, const int* kstart, double2* cx, double2* cp,
+                       double2* xi_a, double2* carry, int* active, hipStream_t s) {
     dim3 g((st.ng + kT - 1) / kT, st.w);
-    hipLaunchKernelGGL(k_chunk_coef, g, dim3(kT), 0, s, st, k0, cx, cp, xi_a, carry, active);
+    hipLaunchKernelGGL(k_chunk_coef, g, dim3(kT), 0, s, st, kstart, cx, cp, xi_a, carry, active);
 }
 
-void launch_gemm_xp(const double2* ring, int ring_len, int w, int n_rows, int k0,
+void launch_gemm_xp(const double2* ring, int ring_len, int w, int n_rows, const int* kstart,
                     const IterState& st, const double2* cx, const double2* cp,
                     const double2* xi_a, const int* active, double2* X, double2* P,
                     hipStream_t s) {
     dim3 g((n_rows + TM - 1) / TM, (st.ng + TN - 1) / TN, w);
-    hipLaunchKernelGGL(k_gemm_xp, g, dim3(kT), 0, s, ring, ring_len, w, n_rows, k0, st, cx, cp,
-                       xi_a, active, X, P);
+    hipLaunchKernelGGL(k_gemm_xp, g, dim3(kT), 0, s, ring, ring_len, w, n_rows, kstart, st, cx,
+                       cp, xi_a, active, X, P);
 }
 
 void launch_t_from_x(const double2* X, int n_rows, int w, int ng, const double* row_w,
-                     const double* col_w, double* t, hipStream_t s) {
-    hipLaunchKernelGGL(k_t_from_x, dim3(ng, w), dim3(kT), 0, s, X, n_rows, ng, row_w, col_w, t);
+                     const double* col_w, const int* only, double* t, hipStream_t s) {
+    hipLaunchKernelGGL(k_t_from_x, dim3(ng, w), dim3(kT), 0, s, X, n_rows, ng, row_w, col_w, only,
+                       t);
 }
 
 void launch_copy_out(const double2* X, int n_rows, int w, int ng, double2* out, int64_t col_stride,
