@@ -244,6 +244,22 @@ negf_status negf_transmission_grad(negf_op* op, const negf_opts* opts, int32_t n
                                    const double* energies, const double* weights,
                                    double* dL_dV, double* T);
 
+/* Landauer current of Eq. 1 from a transmission curve, on the device:
+ *   I(V_b) = (1/pi) int T(E) [f(E - mu_L) - f(E - mu_R)] dE   (atomic units,
+ *   2e/h = 1/pi), mu_{L,R} = e_fermi +- V_b / 2, f the Fermi function at
+ *   temperature kT (Ha; 0 gives a step with f(0) = 1/2),
+ * by the trapezoid rule on the given energy grid (the bias window should lie
+ * inside it; outside the grid T counts as zero).
+ *   n_e >= 2 energies, strictly increasing (host or device), and T[n_e] (host
+ *   or device, e.g. the output of negf_transmission);
+ *   n_bias bias voltages V_b (Ha/e; host or device); current[n_bias] output
+ *   (host or device).  stream: hipStream_t or NULL (the null stream).
+ * Invalid arguments (non-finite or unsorted energies, kT < 0, null
+ * pointers) are rejected before any device call.  Needs no operator. */
+negf_status negf_current(int32_t n_e, const double* energies, const double* T, int32_t n_bias,
+                         const double* bias, double e_fermi, double kT, double* current,
+                         void* stream);
+
 /* Frees the op and all device memory it owns.  NULL is a no-op. */
 void negf_destroy(negf_op* op);
 

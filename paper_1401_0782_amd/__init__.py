@@ -18,6 +18,7 @@ from .api import (  # noqa: F401
     Operator,
     negf_apply_operator,
     negf_build_operator,
+    negf_current,
     negf_solve_columns,
     negf_transmission,
     negf_transmission_batch,

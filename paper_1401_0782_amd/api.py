@@ -254,6 +254,20 @@ def negf_set_launch_shape(op: Operator, block_width: int = 0, wg_target: int = 0
                                         int(plane_kernel)))
 
 
+def negf_current(energies, T, bias, e_fermi: float, kT: float = 0.0, stream=None):
+    """Landauer current I(V) (Eq. 1, atomic units) for each bias in `bias`
+    from T(E) on the energy grid, computed on the device."""
+    e = np.ascontiguousarray(energies, dtype=np.float64)
+    t = np.ascontiguousarray(T, dtype=np.float64)
+    b = np.ascontiguousarray(np.atleast_1d(bias), dtype=np.float64)
+    if t.shape != e.shape:
+        raise ValueError("T must match energies")
+    out = np.zeros(b.size)
+    _check(_lib().negf_current(e.size, _ptr(e), _ptr(t), b.size, _ptr(b), float(e_fermi),
+                               float(kT), _ptr(out), C.c_void_p(stream) if stream else None))
+    return out
+
+
 def negf_transmission_batch(ops, energies_list, max_concurrent=0, check=True, **opts):
     """T(E) for many junctions at once; returns (list of T arrays, statuses)."""
     n = len(ops)

@@ -1637,6 +1637,71 @@ extern "C" negf_status negf_tune(negf_op* op, const negf_opts* opts, int32_t n_e
     return tune_impl(op, opts, n_e, energies, probe_iters, result);
 }
 
+void launch_landauer(const double* e, const double* t, int n_e, const double* bias, int n_bias,
+                     double e_fermi, double kt, double* out, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// negf_current: Landauer current (Eq. 1)
+// ---------------------------------------------------------------------------
+extern "C" negf_status negf_current(int32_t n_e, const double* energies, const double* T,
+                                    int32_t n_bias, const double* bias, double e_fermi, double kT,
+                                    double* current, void* stream) {
+    (void)hipGetLastError();  // a stale error of an earlier call must not fail this one
+    if (n_e < 2 || n_bias < 1 || !energies || !T || !bias || !current) {
+        set_error("negf_current needs n_e >= 2, n_bias >= 1 and non-null arrays");
+        return NEGF_E_INVALID_ARG;
+    }
+    if (!(kT >= 0.0) || !std::isfinite(kT) || !std::isfinite(e_fermi)) {
+        set_error("kT must be finite and >= 0, e_fermi finite");
+        return NEGF_E_INVALID_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // host copies of the inputs (validated here), whatever side they live on
+    std::vector<double> he(n_e), ht(n_e), hb(n_bias);
+    auto fetch = [&](const double* src, double* dst, size_t n) -> negf_status {
+        if (is_device_ptr(src)) {
+            HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        } else {
+            std::memcpy(dst, src, n * sizeof(double));
+        }
+        return NEGF_OK;
+    };
+    CHK(fetch(energies, he.data(), n_e));
+    CHK(fetch(T, ht.data(), n_e));
+    CHK(fetch(bias, hb.data(), n_bias));
+    for (int i = 0; i < n_e; ++i) {
+        if (!std::isfinite(he[i]) || !std::isfinite(ht[i]) || (i > 0 && !(he[i] > he[i - 1]))) {
+            set_error("energies must be finite and strictly increasing, T finite (index %d)", i);
+            return NEGF_E_INVALID_ARG;
+        }
+    }
+    for (int b = 0; b < n_bias; ++b) {
+        if (!std::isfinite(hb[b])) {
+            set_error("bias %d not finite", b);
+            return NEGF_E_INVALID_ARG;
+        }
+    }
+    double* buf = nullptr;
+    const size_t n_buf = 2 * (size_t)n_e + 2 * (size_t)n_bias;
+    CHK(dev_alloc((void**)&buf, n_buf * sizeof(double)));
+    double *de = buf, *dt = buf + n_e, *db = buf + 2 * n_e, *dout = db + n_bias;
+    negf_status st = NEGF_OK;
+    auto run = [&]() -> negf_status {
+        HIPCHK(hipMemcpyAsync(de, he.data(), n_e * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(dt, ht.data(), n_e * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(db, hb.data(), n_bias * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_landauer(de, dt, n_e, db, n_bias, e_fermi, kT, dout, s);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(current, dout, n_bias * sizeof(double), hipMemcpyDefault, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return NEGF_OK;
+    };
+    st = run();
+    (void)hipFree(buf);
+    return st;
+}
+
 extern "C" negf_status negf_set_launch_shape(negf_op* op, int32_t block_width, int32_t wg_target,
                                              int32_t plane_kernel) {
     if (!op) {

@@ -126,3 +126,20 @@ def test_set_launch_shape_validates_without_device():
     lib = _abi.load()
     assert lib.negf_set_launch_shape(None, 64, 256, 1) == _abi.NEGF_E_INVALID_ARG
     assert b"null op" in lib.negf_last_error()
+
+
+def test_current_validates_before_device():
+    from paper_1401_0782_amd import _abi
+
+    lib = _abi.load()
+    e = np.array([0.1, 0.3, 0.2])  # not increasing
+    t = np.ones(3)
+    b = np.array([0.1])
+    out = np.zeros(1)
+    args = (e.ctypes.data, t.ctypes.data, 1, b.ctypes.data, 0.2, 0.0, out.ctypes.data, None)
+    assert lib.negf_current(3, *args) == _abi.NEGF_E_INVALID_ARG
+    assert b"increasing" in lib.negf_last_error()
+    assert lib.negf_current(1, *args) == _abi.NEGF_E_INVALID_ARG
+    e2 = np.array([0.1, 0.2, 0.3])
+    assert lib.negf_current(3, e2.ctypes.data, t.ctypes.data, 1, b.ctypes.data, 0.2, -1.0,
+                            out.ctypes.data, None) == _abi.NEGF_E_INVALID_ARG

@@ -1,0 +1,63 @@
+"""CAP variants through the C ABI: the Gaussian of Eq. 5 and monomial ramps,
+against the oracle, and the calibration plateau on an empty lead."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import end_gaussian_cap, make_custom, power_cap, with_caps
+
+pytestmark = pytest.mark.gpu
+
+NX = NY = 4
+H, R, NCAP = 0.5, 2, 40
+NZ = 2 * NCAP + 10
+
+
+def _mids():
+    thr = O.transverse_thresholds(NX, NY, H, R)
+    uniq = np.unique(np.round(thr, 10))
+    mids = 0.5 * (uniq[:-1] + uniq[1:])[:3]
+    return mids, np.array([np.count_nonzero(thr < E) for E in mids])
+
+
+CAPS = {
+    "gauss_w1_s8": lambda: end_gaussian_cap(NZ, H, NCAP, 8.0, 1.0),
+    "gauss_w2_s8": lambda: end_gaussian_cap(NZ, H, NCAP, 8.0, 2.0),
+    "gauss_w1_s9.84": lambda: end_gaussian_cap(NZ, H, NCAP, 9.84, 1.0),
+    "gauss_w2_s9.84": lambda: end_gaussian_cap(NZ, H, NCAP, 9.84, 2.0),
+    "power2": lambda: power_cap(NZ, NCAP, 2.0, 2),
+    "power4": lambda: power_cap(NZ, NCAP, 2.0, 4),
+}
+
+
+@pytest.mark.parametrize("cap", sorted(CAPS))
+@pytest.mark.parametrize("core", ["multishift", "per_energy"])
+def test_cap_variant_matches_oracle_and_mode_count(gpu_lib, cap, core):
+    import paper_1401_0782_amd as P
+
+    mids, expect = _mids()
+    wire = with_caps(make_custom(NX, NY, NZ, H, R, NCAP, mids), *CAPS[cap]())
+    op = P.operator_from_wire(wire)
+    c = P.NEGF_CORE_MULTISHIFT if core == "multishift" else P.NEGF_CORE_PER_ENERGY
+    T = P.negf_transmission(op, mids, tol=1e-12, core=c)
+    T_ref = O.transmission(wire, mids, method="dense")
+    assert np.max(np.abs(T - T_ref)) <= 1e-8
+    assert np.max(np.abs(T - expect)) < 5e-4
+
+
+def test_gaussian_cap_on_a_wire_with_projectors(gpu_lib):
+    """A Gaussian CAP on a wire with wells and projectors (CAP-free interior)."""
+    import paper_1401_0782_amd as P
+
+    nx, ny, nz, h, ncap = 7, 6, 44, 0.5, 10
+    cx, cy = (nx + 1) * h / 2, (ny + 1) * h / 2
+    wells = [(cx + 0.3, cy - 0.2, 10.0, 0.4), (cx - 0.4, cy + 0.3, 13.0, 0.5)]
+    E = np.linspace(0.3, 1.3, 7)
+    base = make_custom(nx, ny, nz, h, 3, ncap, E, wells=wells,
+                       atoms_kb=[(0.8, 0.3, 0.1), (0.7, 0.2, 0.15)])
+    wire = with_caps(base, *end_gaussian_cap(nz, h, ncap, 2.5, 1.0))
+    op = P.operator_from_wire(wire)
+    T = P.negf_transmission(op, E, tol=1e-12)
+    T_ref = O.transmission(wire, E, method="dense")
+    assert np.max(np.abs(T - T_ref)) <= 1e-8

@@ -159,6 +159,30 @@ def test_empty_wire_counts_open_modes():
     assert np.max(np.abs(T - expect)) < 1e-4, (T, expect)
 
 
+def test_cap_calibration_plateau_on_empty_wire():
+    """The paper's CAP calibration (Sec. III.A): on a long empty lead the
+    transmission stays at the open-mode count while the Gaussian CAP of Eq. 5
+    changes by 100 % in height and 23 % in width, and for monomial ramps."""
+    from workloads import end_gaussian_cap, power_cap, with_caps
+
+    nx = ny = 4
+    h, R, ncap = 0.5, 2, 40
+    thr = O.transverse_thresholds(nx, ny, h, R)
+    uniq = np.unique(np.round(thr, 10))
+    mids = 0.5 * (uniq[:-1] + uniq[1:])[:3]
+    expect = np.array([np.count_nonzero(thr < E) for E in mids])
+    nz = 2 * ncap + 10
+    base = make_custom(nx, ny, nz, h, R, ncap, mids)
+    caps = [end_gaussian_cap(nz, h, ncap, s, w0) for w0 in (1.0, 2.0) for s in (8.0, 8.0 * 1.23)]
+    caps += [power_cap(nz, ncap, 2.0, order) for order in (2, 4)]
+    for left, right in caps:
+        T = O.transmission(with_caps(base, left, right), mids, method="dense")
+        assert np.max(np.abs(T - expect)) < 5e-4, T
+    # a CAP far too weak for this lead reflects: the plateau has an edge
+    T = O.transmission(with_caps(base, *end_gaussian_cap(nz, h, ncap, 6.0, 0.25)), mids, method="dense")
+    assert np.max(np.abs(T - expect)) > 0.1
+
+
 # ---------------------------------------------------------------- identities
 @pytest.fixture(scope="module")
 def small_wire():
@@ -247,3 +271,18 @@ def test_landauer_constant_transmission():
     assert abs(I - 0.7 * 0.2 / np.pi) < 1e-12
     assert abs(O.landauer_current(E, T, bias=0.2, e_fermi=0.0, kT=0.01) - 0.7 * 0.2 / np.pi) < 1e-6
     assert O.landauer_current(E, T, bias=-0.2, e_fermi=0.0) == pytest.approx(-0.7 * 0.2 / np.pi)
+
+
+def test_landauer_linear_transmission_closed_form():
+    """T(E) = a + b E, zero temperature, bias window on grid points: the
+    trapezoid rule is exact, I = (1/pi) [a V + b (mu_L^2 - mu_R^2) / 2]."""
+    E = np.arange(-256, 257) / 256.0  # binary spacing: every chemical potential below is a grid point
+    a, b = 0.3, 1.7
+    T = a + b * E
+    for ef, V in [(0.125, 0.25), (-0.25, 0.5), (0.0, -0.375)]:
+        mu_l, mu_r = ef + V / 2, ef - V / 2
+        exact = (a * V + b * (mu_l ** 2 - mu_r ** 2) / 2) / np.pi
+        assert O.landauer_current(E, T, bias=V, e_fermi=ef, kT=0.0) == pytest.approx(exact, abs=1e-14)
+    # at finite temperature the window integrates to V for any E_F deep inside the grid
+    assert O.landauer_current(E, np.ones_like(E), bias=0.1, e_fermi=0.0, kT=0.02) == \
+        pytest.approx(0.1 / np.pi, rel=1e-9)

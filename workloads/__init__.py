@@ -18,4 +18,7 @@ from .wires import (  # noqa: F401
     well_basis,
     potential_from_amplitudes,
     quartic_cap,
+    power_cap,
+    end_gaussian_cap,
+    with_caps,
 )

@@ -78,15 +78,41 @@ class Wire:
 # building blocks
 # ----------------------------------------------------------------------------
 
-def quartic_cap(nz: int, n_cap: int, w0: float = CAP_PEAK):
-    """Per-plane CAP profiles (left, right), each (nz,)."""
+def power_cap(nz: int, n_cap: int, w0: float = CAP_PEAK, order: int = 4):
+    """Monomial ramp CAP W_q = w0 (q / n_cap)^order on the n_cap end planes
+    (q = 1 innermost .. n_cap outermost); per-plane (left, right), each (nz,)."""
     left = np.zeros(nz)
     right = np.zeros(nz)
     for q in range(1, n_cap + 1):
-        val = w0 * (q / n_cap) ** 4
+        val = w0 * (q / n_cap) ** order
         left[n_cap - q] = val  # q = n_cap -> plane 0 (outermost)
         right[nz - n_cap - 1 + q] = val  # q = n_cap -> plane nz-1
     return left, right
+
+
+def quartic_cap(nz: int, n_cap: int, w0: float = CAP_PEAK):
+    """Per-plane CAP profiles (left, right), each (nz,): the order-4 ramp."""
+    return power_cap(nz, n_cap, w0, 4)
+
+
+def end_gaussian_cap(nz: int, h: float, n_cap: int, sigma: float, w0: float):
+    """Gaussian CAP of Eq. (5) centred on the outermost plane of each end and
+    kept on the n_cap end planes (zero further in, where it has decayed below
+    w0 exp(-(n_cap h / sigma)^2)), so that the two absorbing regions stay
+    disjoint."""
+    z = np.arange(nz)
+    left = np.where(z < n_cap, w0 * np.exp(-((z * h) ** 2) / sigma ** 2), 0.0)
+    right = np.where(z >= nz - n_cap, w0 * np.exp(-(((nz - 1 - z) * h) ** 2) / sigma ** 2), 0.0)
+    return left, right
+
+
+def with_caps(wire, left, right, name=None):
+    """A copy of wire with other per-plane CAP profiles."""
+    import dataclasses
+
+    return dataclasses.replace(wire, cap_left=np.asarray(left, float),
+                               cap_right=np.asarray(right, float),
+                               name=name or wire.name)
 
 
 def gaussian_cap(nz: int, h: float, z_left: float, z_right: float,
