@@ -175,6 +175,121 @@ __global__ __launch_bounds__(kT) void k_gemm_xp(const double2* __restrict__ ring
     }
 }
 
+// The same update on the matrix cores (v_mfma_f64_16x16x4f64).  Lane layout
+// of that instruction: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// and holds D[4 i + l / 16][l % 16], i = 0..3.  A complex product takes four
+// real ones: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.  A work-group of four
+// waves owns 64 rows x 32 energies; each wave 32 rows x 16 energies as two
+// 16 x 16 blocks for X and two for P (eight accumulators), which keeps the
+// register count low enough for several work-groups per CU.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+constexpr int MK = 16;   // chunk iterations staged per LDS pass
+constexpr int MTN = 32;  // energies per work-group
+
+__device__ inline d4_t mfma4(double a, double b, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(kT) void k_gemm_xp_mfma(const double2* __restrict__ ring, int ring_len,
+                                                     int w, int n_rows,
+                                                     const int* __restrict__ kstart, IterState st,
+                                                     const double2* __restrict__ cx,
+                                                     const double2* __restrict__ cp,
+                                                     const double2* __restrict__ xi_a,
+                                                     const int* __restrict__ active,
+                                                     double2* __restrict__ X,
+                                                     double2* __restrict__ P) {
+    __shared__ double2 sR[MK][TM];
+    __shared__ double2 sX[MK][MTN];
+    __shared__ double2 sP[MK][MTN];
+    __shared__ int any_active;
+    const int c = blockIdx.z;
+    const int row0 = blockIdx.x * TM;
+    const int g0 = blockIdx.y * MTN;
+    const int ng = st.ng, ch = st.chunk;
+    const int k0 = kstart[c];
+    const int cl = max(0, min(ch, st.k[c] - k0));
+    if (cl == 0) return;
+    const int tid = threadIdx.x;
+    if (tid == 0) any_active = 0;
+    __syncthreads();
+    if (tid < MTN && g0 + tid < ng && active[(int64_t)c * ng + g0 + tid]) any_active = 1;
+    __syncthreads();
+    if (!any_active) return;
+    const int lane = tid % 64, wave = tid / 64;
+    const int wr = (wave & 1) * 32, wc = (wave >> 1) * 16;  // the wave's rows / energies
+    const int lr = lane % 16, lk = lane / 16;
+    const d4_t zero4 = {0.0, 0.0, 0.0, 0.0};
+    d4_t axr[2] = {zero4, zero4}, axi[2] = {zero4, zero4};
+    d4_t apr[2] = {zero4, zero4}, api[2] = {zero4, zero4};
+    const double2* CX = cx + (int64_t)c * ch * ng;
+    const double2* CP = cp + (int64_t)c * ch * ng;
+    for (int j0 = 0; j0 < cl; j0 += MK) {
+        for (int e = tid; e < MK * TM; e += kT) {
+            const int jj = e / TM, rr = e % TM;
+            const int j = j0 + jj, row = row0 + rr;
+            double2 v = mk(0.0, 0.0);
+            if (j < cl && row < n_rows) {
+                const int slot = (k0 + j) % ring_len;
+                v = ring[((int64_t)slot * w + c) * n_rows + row];
+            }
+            sR[jj][rr] = v;
+        }
+        for (int e = tid; e < MK * MTN; e += kT) {
+            const int jj = e / MTN, gg = e % MTN;
+            const int j = j0 + jj, g = g0 + gg;
+            double2 vx = mk(0.0, 0.0), vp = mk(0.0, 0.0);
+            if (j < cl && g < ng) {
+                vx = CX[(int64_t)j * ng + g];
+                vp = CP[(int64_t)j * ng + g];
+            }
+            sX[jj][gg] = vx;
+            sP[jj][gg] = vp;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int kk = 0; kk < MK; kk += 4) {
+            const double2 a0 = sR[kk + lk][wr + lr];
+            const double2 a1 = sR[kk + lk][wr + 16 + lr];
+            const double2 bx = sX[kk + lk][wc + lr];
+            const double2 bp = sP[kk + lk][wc + lr];
+            axr[0] = mfma4(a0.x, bx.x, axr[0]);
+            axr[0] = mfma4(-a0.y, bx.y, axr[0]);
+            axi[0] = mfma4(a0.x, bx.y, axi[0]);
+            axi[0] = mfma4(a0.y, bx.x, axi[0]);
+            axr[1] = mfma4(a1.x, bx.x, axr[1]);
+            axr[1] = mfma4(-a1.y, bx.y, axr[1]);
+            axi[1] = mfma4(a1.x, bx.y, axi[1]);
+            axi[1] = mfma4(a1.y, bx.x, axi[1]);
+            apr[0] = mfma4(a0.x, bp.x, apr[0]);
+            apr[0] = mfma4(-a0.y, bp.y, apr[0]);
+            api[0] = mfma4(a0.x, bp.y, api[0]);
+            api[0] = mfma4(a0.y, bp.x, api[0]);
+            apr[1] = mfma4(a1.x, bp.x, apr[1]);
+            apr[1] = mfma4(-a1.y, bp.y, apr[1]);
+            api[1] = mfma4(a1.x, bp.y, api[1]);
+            api[1] = mfma4(a1.y, bp.x, api[1]);
+        }
+        __syncthreads();
+    }
+    const int g = g0 + wc + lr;
+    if (g >= ng) return;
+    const int64_t o = (int64_t)c * ng + g;
+    const double2 xi = xi_a[2 * o], aa = xi_a[2 * o + 1];
+    double2* Xg = X + o * n_rows;
+    double2* Pg = P + o * n_rows;
+#pragma unroll
+    for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = row0 + wr + 16 * ra + 4 * i + lk;
+            if (row >= n_rows) continue;
+            const double2 p0 = Pg[row];
+            Xg[row] = cadd(cadd(Xg[row], cmul(xi, p0)), mk(axr[ra][i], axi[ra][i]));
+            Pg[row] = cadd(cmul(aa, p0), mk(apr[ra][i], api[ra][i]));
+        }
+}
+
 // t[c][g] = col_w[c] * sum_row row_w[row] |X[c][g][row]|^2, one work-group per (g, c);
 // only (nullable) selects the columns to reduce
 __global__ __launch_bounds__(kT) void k_t_from_x(const double2* __restrict__ X, int n_rows, int ng,
@@ -222,8 +337,15 @@ void launch_gemm_xp(const double2* ring, int ring_len, int w, int n_rows, const 
                     const double2* xi_a, const int* active, double2* X, double2* P,
                     hipStream_t s) {
     dim3 g((n_rows + TM - 1) / TM, (st.ng + TN - 1) / TN, w);
-    hipLaunchKernelGGL(k_gemm_xp, g, dim3(kT), 0, s, ring, ring_len, w, n_rows, kstart, st, cx,
-                       cp, xi_a, active, X, P);
+    // NEGF_GEMM_VALU=1 selects the vector-ALU kernel (read per chunk)
+    const char* env = getenv("NEGF_GEMM_VALU");
+    const bool valu = env && env[0] == '1';
+    if (valu)
+        hipLaunchKernelGGL(k_gemm_xp, g, dim3(kT), 0, s, ring, ring_len, w, n_rows, kstart, st, cx,
+                           cp, xi_a, active, X, P);
+    else
+        hipLaunchKernelGGL(k_gemm_xp_mfma, dim3(g.x, (st.ng + MTN - 1) / MTN, w), dim3(kT), 0, s,
+                           ring, ring_len, w, n_rows, kstart, st, cx, cp, xi_a, active, X, P);
 }
 
 void launch_t_from_x(const double2* X, int n_rows, int w, int ng, const double* row_w,

@@ -69,3 +69,28 @@ def test_streaming_shard_and_max_iter(gpu_lib):
     assert np.array_equal(d_s.t_col, d_b.t_col)
     assert np.array_equal(d_s.item_status, d_b.item_status)
     assert (d_s.iters <= 20).all()
+
+
+def test_mfma_and_valu_shift_accumulation_agree(gpu_lib):
+    """The blocked shift accumulation on the matrix cores and on the vector
+    ALUs give the same T(E) to rounding, and both the oracle's."""
+    import paper_1401_0782_amd as P
+
+    wire = make_wire(1)
+    op = P.operator_from_wire(wire)
+    old = os.environ.get("NEGF_GEMM_VALU")
+    try:
+        os.environ["NEGF_GEMM_VALU"] = "0"
+        T_m, d_m = P.negf_transmission(op, wire.energies, n_cols=384, tol=1e-12)
+        os.environ["NEGF_GEMM_VALU"] = "1"
+        T_v, d_v = P.negf_transmission(op, wire.energies, n_cols=384, tol=1e-12)
+    finally:
+        if old is None:
+            del os.environ["NEGF_GEMM_VALU"]
+        else:
+            os.environ["NEGF_GEMM_VALU"] = old
+    assert np.array_equal(d_m.iters, d_v.iters)
+    np.testing.assert_allclose(d_m.t_col, d_v.t_col, rtol=1e-11, atol=1e-24)
+    T_ref = O.transmission(wire, method="dense")
+    assert np.max(np.abs(T_m - T_ref)) <= 1e-8
+    assert np.max(np.abs(T_v - T_ref)) <= 1e-8
