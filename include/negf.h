@@ -260,6 +260,25 @@ negf_status negf_current(int32_t n_e, const double* energies, const double* T, i
                          const double* bias, double e_fermi, double kT, double* current,
                          void* stream);
 
+/* The complex-energy diagonalisation route of Sec. II.C (Eqs. 8-13) from
+ * eigenpairs (eps_i, U_i) of H_op = H - i(W_L + W_R) for this op's H and CAPs,
+ * supplied by the caller (the paper obtains them with ARPACK):
+ *   T(E) = sum_ij Gt_L,ij Gt_R,ji / ((E - eps_j)(E - conj(eps_i)))   (Eq. 13),
+ *   Gt_L = U^H Gamma_L U,  Gt_R = U^T Gamma_R conj(U),  Gamma = 2W    (Eq. 12),
+ * with the eigenvectors complex-normalised, U_i^T U_i = 1 (Eqs. 9-11).  With
+ * every eigenpair this equals negf_transmission's T(E); keep in (0, 1) keeps
+ * the round(keep * n_r) eigenpairs whose real parts lie nearest the middle of
+ * the energy window (ties by index), the truncation of Sec. II.D, whose
+ * missing poles are the route's known artefact; keep 0 or 1 keeps all.
+ *   eps    n_r host eigenvalues;  U  [n_r][N] eigenvectors, each contiguous
+ *          (host or device);  energies  n_e host values;  T  n_e host output.
+ * The Gram products over the CAP rows and the double sum over all energies
+ * run on the FP64 matrix cores.  Rejects non-finite input and energies that
+ * coincide with a kept eigenvalue. */
+negf_status negf_spectral_transmission(negf_op* op, int32_t n_r, const negf_c64* eps,
+                                       const negf_c64* U, double keep, int32_t n_e,
+                                       const double* energies, double* T);
+
 /* Frees the op and all device memory it owns.  NULL is a no-op. */
 void negf_destroy(negf_op* op);
 

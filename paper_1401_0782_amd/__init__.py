@@ -20,6 +20,7 @@ from .api import (  # noqa: F401
     negf_build_operator,
     negf_current,
     negf_solve_columns,
+    negf_spectral_transmission,
     negf_transmission,
     negf_transmission_batch,
     negf_transmission_grad,

@@ -31,6 +31,7 @@ EXPORTS = (
     "negf_tune",
     "negf_set_launch_shape",
     "negf_current",
+    "negf_spectral_transmission",
     "negf_transmission_grad",
     "negf_destroy",
     "negf_last_error",
@@ -104,6 +105,8 @@ def load(path: str | None = None):
     lib.negf_tune.argtypes = [vp, C.POINTER(negf_opts), C.c_int32, vp, C.c_int32,
                               C.POINTER(negf_tune_result)]
     lib.negf_set_launch_shape.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+    lib.negf_spectral_transmission.argtypes = [vp, C.c_int32, vp, vp, C.c_double, C.c_int32, vp,
+                                               vp]
     lib.negf_current.argtypes = [C.c_int32, vp, vp, C.c_int32, vp, C.c_double, C.c_double, vp, vp]
     lib.negf_destroy.argtypes = [vp]
     lib.negf_destroy.restype = None
@@ -111,7 +114,8 @@ def load(path: str | None = None):
     lib.negf_version.restype = C.c_char_p
     for name in ("negf_build_operator", "negf_apply_operator", "negf_solve_columns",
                  "negf_transmission", "negf_transmission_grad", "negf_transmission_batch",
-                 "negf_tune", "negf_set_launch_shape", "negf_current"):
+                 "negf_tune", "negf_set_launch_shape", "negf_current",
+                 "negf_spectral_transmission"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

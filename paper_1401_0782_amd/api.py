@@ -254,6 +254,23 @@ def negf_set_launch_shape(op: Operator, block_width: int = 0, wg_target: int = 0
                                         int(plane_kernel)))
 
 
+def negf_spectral_transmission(op: Operator, eps, U, energies, keep: float = 1.0):
+    """T(E) by the complex-energy diagonalisation route (Eqs. 8-13) from
+    eigenpairs of H - iW: eps (n_r,), U (n_r, N) with each row an eigenvector
+    normalised to U_i^T U_i = 1 (numpy or a torch device tensor).  keep in
+    (0, 1) truncates to the eigenpairs nearest the window."""
+    e = np.ascontiguousarray(energies, dtype=np.float64)
+    ev = _c64(np.asarray(eps))
+    if isinstance(U, np.ndarray):
+        U = _c64(U)
+    if tuple(U.shape) != (ev.size, op.N):
+        raise ValueError("U must be (n_r, N)")
+    T = np.zeros(e.size)
+    _check(_lib().negf_spectral_transmission(op.handle, ev.size, _ptr(ev), _ptr(U), float(keep),
+                                             e.size, _ptr(e), _ptr(T)))
+    return T
+
+
 def negf_current(energies, T, bias, e_fermi: float, kT: float = 0.0, stream=None):
     """Landauer current I(V) (Eq. 1, atomic units) for each bias in `bias`
     from T(E) on the energy grid, computed on the device."""

@@ -1702,6 +1702,122 @@ extern "C" negf_status negf_current(int32_t n_e, const double* energies, const d
     return st;
 }
 
+void launch_gram(const double2* U, int64_t N, const int* sel, int n_r, int64_t row0, int n_rows,
+                 const double* d, const double2* prev, double2* out, hipStream_t s);
+int eq13_tiles(int n_r);
+void launch_eq13(const double2* M, int n_r, const double2* eps, const double* energies, int n_e,
+                 double* part, double* T, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// negf_spectral_transmission: Eqs. 8-13 from caller-supplied eigenpairs
+// ---------------------------------------------------------------------------
+static negf_status spectral_impl(negf_op* op, int32_t n_r, const negf_c64* eps,
+                                 const negf_c64* U, double keep, int32_t n_e,
+                                 const double* energies, double* T) {
+    if (n_r < 1 || !eps || !U || !T) {
+        set_error("need n_r >= 1, eps, U and T");
+        return NEGF_E_INVALID_ARG;
+    }
+    if (!(keep >= 0.0 && keep <= 1.0)) {
+        set_error("keep must lie in [0, 1]");
+        return NEGF_E_INVALID_ARG;
+    }
+    CHK(check_energies(n_e, energies));
+    for (int i = 0; i < n_r; ++i) {
+        if (!std::isfinite(eps[i].re) || !std::isfinite(eps[i].im)) {
+            set_error("eigenvalue %d not finite", i);
+            return NEGF_E_INVALID_ARG;
+        }
+    }
+    // the kept eigenpairs: all, or those nearest the middle of the window
+    double emin = energies[0], emax = energies[0];
+    for (int e = 0; e < n_e; ++e) {
+        emin = std::min(emin, energies[e]);
+        emax = std::max(emax, energies[e]);
+    }
+    std::vector<int> sel(n_r);
+    for (int i = 0; i < n_r; ++i) sel[i] = i;
+    int n_keep = n_r;
+    if (keep > 0.0 && keep < 1.0) {
+        const double mid = 0.5 * (emin + emax);
+        std::stable_sort(sel.begin(), sel.end(), [&](int a, int b) {
+            return std::fabs(eps[a].re - mid) < std::fabs(eps[b].re - mid);
+        });
+        n_keep = std::max(1, (int)std::lround(keep * n_r));
+        sel.resize(n_keep);
+    }
+    std::vector<double2> eps_k(n_keep);
+    for (int i = 0; i < n_keep; ++i) {
+        eps_k[i] = make_double2(eps[sel[i]].re, eps[sel[i]].im);
+        for (int e = 0; e < n_e; ++e) {
+            if (energies[e] == eps_k[i].x && eps_k[i].y == 0.0) {
+                set_error("energy %d coincides with eigenvalue %d", e, sel[i]);
+                return NEGF_E_INVALID_ARG;
+            }
+        }
+    }
+    HIPCHK(hipSetDevice(op->device));
+    hipStream_t s = op->own_stream;
+    const int64_t N = op->N, plane = (int64_t)op->nx * op->ny;
+    const int64_t rowL = (int64_t)op->zl0 * plane, rowR = (int64_t)op->zr0 * plane;
+    const int nL = (int)((op->zl1 - op->zl0) * plane), nR = (int)((op->zr1 - op->zr0) * plane);
+    std::vector<double> dL(nL), dR(nR);
+    for (int r = 0; r < nL; ++r) dL[r] = 2.0 * op->cap_l[op->zl0 + r / plane];
+    for (int r = 0; r < nR; ++r) dR[r] = 2.0 * op->cap_r[op->zr0 + r / plane];
+    // device buffers: one allocation, freed on return
+    const size_t b_u = is_device_ptr(U) ? 0 : (size_t)n_r * N * sizeof(double2);
+    const size_t b_m = (size_t)n_keep * n_keep * sizeof(double2);
+    const size_t b_eps = (size_t)n_keep * sizeof(double2);
+    const size_t b_sel = ((size_t)n_keep * sizeof(int) + 255) & ~(size_t)255;
+    const size_t b_d = (size_t)(nL + nR) * sizeof(double);
+    const size_t b_e = (size_t)n_e * sizeof(double) * (2 + eq13_tiles(n_keep));
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    char* base = nullptr;
+    CHK(dev_alloc((void**)&base, al(b_u) + al(b_m) + al(b_eps) + al(b_sel) + al(b_d) + al(b_e)));
+    size_t off = 0;
+    auto take = [&](size_t b) { char* p = base + off; off += al(b); return p; };
+    double2* d_u = b_u ? (double2*)take(b_u) : (double2*)U;
+    double2* d_m = (double2*)take(b_m);
+    double2* d_eps = (double2*)take(b_eps);
+    int* d_sel = (int*)take(b_sel);
+    double* d_d = (double*)take(b_d);
+    double* d_e = (double*)take(b_e);
+    double* d_t = d_e + n_e;
+    double* d_part = d_t + n_e;
+    auto run = [&]() -> negf_status {
+        if (b_u)
+            HIPCHK(hipMemcpyAsync(d_u, U, b_u, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_eps, eps_k.data(), b_eps, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_sel, sel.data(), n_keep * sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_d, dL.data(), nL * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_d + nL, dR.data(), nR * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_e, energies, n_e * sizeof(double), hipMemcpyHostToDevice, s));
+        // M = (U^H Gamma_L U) o (U^H Gamma_R U), then T(E) = Re(a^H M a)
+        launch_gram(d_u, N, d_sel, n_keep, rowL, nL, d_d, nullptr, d_m, s);
+        launch_gram(d_u, N, d_sel, n_keep, rowR, nR, d_d + nL, d_m, d_m, s);
+        launch_eq13(d_m, n_keep, d_eps, d_e, n_e, d_part, d_t, s);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(T, d_t, n_e * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return NEGF_OK;
+    };
+    const negf_status st = run();
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(base);
+    return st;
+}
+
+extern "C" negf_status negf_spectral_transmission(negf_op* op, int32_t n_r, const negf_c64* eps,
+                                                  const negf_c64* U, double keep, int32_t n_e,
+                                                  const double* energies, double* T) {
+    (void)hipGetLastError();  // a stale error of an earlier call must not fail this one
+    if (!op) {
+        set_error("null op");
+        return NEGF_E_INVALID_ARG;
+    }
+    return spectral_impl(op, n_r, eps, U, keep, n_e, energies, T);
+}
+
 extern "C" negf_status negf_set_launch_shape(negf_op* op, int32_t block_width, int32_t wg_target,
                                              int32_t plane_kernel) {
     if (!op) {

@@ -1,0 +1,172 @@
+// The complex-energy diagonalisation route of Sec. II.C (Eqs. 8-13) on the
+// device, from eigenpairs (eps_i, U_i) of H_op = H - iW with U_i^T U_i = 1.
+//
+// With Gamma = 2W, Eq. 12's matrices are Gt_L = U^H Gamma_L U and
+// Gt_R = U^T Gamma_R U^*.  Both K_L = U^H Gamma_L U and K_R = U^H Gamma_R U are
+// Hermitian and Gt_R = conj(K_R), so Eq. 13's weight Gt_L,ij Gt_R,ji is the
+// elementwise product M_ij = K_L,ij K_R,ij (Hermitian), and
+//     T(E) = sum_ij M_ij a_j conj(a_i) = Re(a^H M a),   a_j = 1 / (E - eps_j).
+// Both stages are dense complex contractions on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64; lane l supplies A[l % 16][l / 16], B[l / 16][l % 16]
+// and holds D[4 i + l / 16][l % 16]): the Gram products over the CAP rows,
+// and Y = M A over all energies with A generated on the fly, reduced to T by
+// conj(A) o Y summed over rows.
+#include "negf_internal.h"
+
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+constexpr int kT = 256;
+constexpr int GT = 32;  // output tile (rows and columns) per work-group
+constexpr int GK = 32;  // contraction slice staged per LDS pass
+
+__device__ inline d4_t mfma4(double a, double b, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// K[i][j] = sum_{r < n_rows} conj(U[i][row0 + r]) d[r] U[j][row0 + r]   (i, j < n_r)
+// and, when prev != null, out = prev o K (elementwise) instead of K.
+// U: [n_r][N] (eigenvector i contiguous); sel: eigenvector index per row of K.
+__global__ __launch_bounds__(kT) void k_gram(const double2* __restrict__ U, int64_t N,
+                                             const int* __restrict__ sel, int n_r, int64_t row0,
+                                             int n_rows, const double* __restrict__ d,
+                                             const double2* __restrict__ prev,
+                                             double2* __restrict__ out) {
+    __shared__ double2 sA[GK][GT + 1];
+    __shared__ double2 sB[GK][GT + 1];
+    const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+    const int wm = (wave & 1) * 16, wn = (wave >> 1) * 16;
+    const int lr = lane % 16, lk = lane / 16;
+    d4_t cr = {0.0, 0.0, 0.0, 0.0}, ci = cr;
+    for (int r0 = 0; r0 < n_rows; r0 += GK) {
+        // stage: one eigenvector per (tile row, slice), the slice contiguous in memory
+        for (int e = tid; e < GT * GK; e += kT) {
+            const int m = e / GK, k = e % GK;
+            const int r = r0 + k;
+            double2 va = mk(0.0, 0.0), vb = mk(0.0, 0.0);
+            if (r < n_rows) {
+                if (i0 + m < n_r) {
+                    const double2 u = U[(int64_t)sel[i0 + m] * N + row0 + r];
+                    va = mk(u.x * d[r], -u.y * d[r]);  // conj(U) d
+                }
+                if (j0 + m < n_r) vb = U[(int64_t)sel[j0 + m] * N + row0 + r];
+            }
+            sA[k][m] = va;
+            sB[k][m] = vb;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int kk = 0; kk < GK; kk += 4) {
+            const double2 a = sA[kk + lk][wm + lr];
+            const double2 b = sB[kk + lk][wn + lr];
+            cr = mfma4(a.x, b.x, cr);
+            cr = mfma4(-a.y, b.y, cr);
+            ci = mfma4(a.x, b.y, ci);
+            ci = mfma4(a.y, b.x, ci);
+        }
+        __syncthreads();
+    }
+    const int j = j0 + wn + lr;
+    if (j >= n_r) return;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int i = i0 + wm + 4 * t + lk;
+        if (i >= n_r) continue;
+        double2 v = mk(cr[t], ci[t]);
+        const int64_t o = (int64_t)i * n_r + j;
+        if (prev) v = cmul(prev[o], v);
+        out[o] = v;
+    }
+}
+
+// part[tile][e] = sum_{i in tile} Re( conj(a_i(E_e)) sum_j M[i][j] a_j(E_e) ),
+// a_j(E) = 1 / (E - eps_j); one work-group per (32 rows i, 32 energies).
+__global__ __launch_bounds__(kT) void k_eq13(const double2* __restrict__ M, int n_r,
+                                             const double2* __restrict__ eps,
+                                             const double* __restrict__ energies, int n_e,
+                                             double* __restrict__ part) {
+    __shared__ double2 sM[GK][GT + 1];
+    __shared__ double2 sA[GK][GT + 1];
+    __shared__ double red[4][16];
+    const int i0 = blockIdx.x * GT, e0 = blockIdx.y * GT;
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+    const int wm = (wave & 1) * 16, wn = (wave >> 1) * 16;
+    const int lr = lane % 16, lk = lane / 16;
+    d4_t cr = {0.0, 0.0, 0.0, 0.0}, ci = cr;
+    for (int j0 = 0; j0 < n_r; j0 += GK) {
+        for (int e = tid; e < GT * GK; e += kT) {
+            const int m = e / GK, k = e % GK;
+            const int j = j0 + k;
+            double2 vm = mk(0.0, 0.0), va = mk(0.0, 0.0);
+            if (j < n_r) {
+                if (i0 + m < n_r) vm = M[(int64_t)(i0 + m) * n_r + j];
+                if (e0 + m < n_e) va = cdiv(mk(1.0, 0.0), mk(energies[e0 + m] - eps[j].x, -eps[j].y));
+            }
+            sM[k][m] = vm;
+            sA[k][m] = va;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int kk = 0; kk < GK; kk += 4) {
+            const double2 a = sM[kk + lk][wm + lr];
+            const double2 b = sA[kk + lk][wn + lr];
+            cr = mfma4(a.x, b.x, cr);
+            cr = mfma4(-a.y, b.y, cr);
+            ci = mfma4(a.x, b.y, ci);
+            ci = mfma4(a.y, b.x, ci);
+        }
+        __syncthreads();
+    }
+    // this lane: Y[i][e] for i = i0 + wm + 4t + lk (t = 0..3), e = e0 + wn + lr
+    const int e = e0 + wn + lr;
+    double s = 0.0;
+    if (e < n_e) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int i = i0 + wm + 4 * t + lk;
+            if (i >= n_r) continue;
+            const double2 ai = cdiv(mk(1.0, 0.0), mk(energies[e] - eps[i].x, -eps[i].y));
+            s += ai.x * cr[t] + ai.y * ci[t];  // Re(conj(a_i) y)
+        }
+    }
+    // the four lanes of one energy (lk = 0..3), then the two waves of one energy column
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    if (lk == 0) red[wave][lr] = s;
+    __syncthreads();
+    if (tid < GT) {
+        const int wc = tid / 16, l = tid % 16;  // energy column half, lane
+        const int ee = e0 + wc * 16 + l;
+        // waves (0, 1) hold energies e0 .. e0 + 15, waves (2, 3) the next 16
+        if (ee < n_e) part[(int64_t)blockIdx.x * n_e + ee] = red[2 * wc][l] + red[2 * wc + 1][l];
+    }
+}
+
+// T[e] = sum over row tiles of part[tile][e], in tile order
+__global__ __launch_bounds__(kT) void k_sum_tiles(const double* __restrict__ part, int n_tiles,
+                                                  int n_e, double* __restrict__ T) {
+    const int e = blockIdx.x * kT + threadIdx.x;
+    if (e >= n_e) return;
+    double s = 0.0;
+    for (int t = 0; t < n_tiles; ++t) s += part[(int64_t)t * n_e + e];
+    T[e] = s;
+}
+
+}  // namespace
+
+void launch_gram(const double2* U, int64_t N, const int* sel, int n_r, int64_t row0, int n_rows,
+                 const double* d, const double2* prev, double2* out, hipStream_t s) {
+    dim3 g((n_r + GT - 1) / GT, (n_r + GT - 1) / GT);
+    hipLaunchKernelGGL(k_gram, g, dim3(kT), 0, s, U, N, sel, n_r, row0, n_rows, d, prev, out);
+}
+
+int eq13_tiles(int n_r) { return (n_r + GT - 1) / GT; }
+
+void launch_eq13(const double2* M, int n_r, const double2* eps, const double* energies, int n_e,
+                 double* part, double* T, hipStream_t s) {
+    dim3 g(eq13_tiles(n_r), (n_e + GT - 1) / GT);
+    hipLaunchKernelGGL(k_eq13, g, dim3(kT), 0, s, M, n_r, eps, energies, n_e, part);
+    hipLaunchKernelGGL(k_sum_tiles, dim3((n_e + kT - 1) / kT), dim3(kT), 0, s, part, eq13_tiles(n_r),
+                       n_e, T);
+}

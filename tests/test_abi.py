@@ -143,3 +143,12 @@ def test_current_validates_before_device():
     e2 = np.array([0.1, 0.2, 0.3])
     assert lib.negf_current(3, e2.ctypes.data, t.ctypes.data, 1, b.ctypes.data, 0.2, -1.0,
                             out.ctypes.data, None) == _abi.NEGF_E_INVALID_ARG
+
+
+def test_spectral_rejects_null_operator():
+    from paper_1401_0782_amd import _abi
+
+    lib = _abi.load()
+    e = np.array([0.3])
+    assert lib.negf_spectral_transmission(None, 1, None, None, 1.0, 1, e.ctypes.data,
+                                          None) == _abi.NEGF_E_INVALID_ARG
