@@ -68,6 +68,14 @@ enum {
     NEGF_CORE_MULTISHIFT = 2  /* one COCG run per column serves every energy */
 };
 
+/* negf_opts.solver */
+enum {
+    NEGF_SOLVER_COCG = 0, /* conjugate orthogonal CG (bilinear form, Eq. 6 symmetry) */
+    NEGF_SOLVER_QMR = 1   /* simplified (symmetric) QMR: the same Lanczos recurrences
+                             with quasi-minimal-residual smoothing of the iterate;
+                             per-energy core only */
+};
+
 /* negf_opts.direction for negf_transmission */
 enum {
     NEGF_DIR_RL = 0, /* columns on the right CAP support, rows on the left */
@@ -94,6 +102,8 @@ typedef struct {
 typedef struct {
     int32_t precision;   /* NEGF_FP64 or NEGF_MIXED */
     int32_t core;        /* NEGF_CORE_* */
+    int32_t solver;      /* NEGF_SOLVER_*; QMR selects the per-energy core under AUTO
+                            and is rejected with NEGF_CORE_MULTISHIFT */
     int32_t direction;   /* NEGF_DIR_* (negf_transmission only) */
     double tol;          /* relative residual per (column, energy); FP64 path:
                             COCG residual estimate; mixed path: true FP64

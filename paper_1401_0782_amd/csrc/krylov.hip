@@ -145,12 +145,19 @@ __global__ __launch_bounds__(kT) void k_r_update(cplx_t<R>* __restrict__ r,
                                                  const int* __restrict__ done,
                                                  const double2* __restrict__ alpha,
                                                  double2* __restrict__ part_rr,
-                                                 double* __restrict__ part_nn) {
+                                                 double* __restrict__ part_nn,
+                                                 const double* __restrict__ qmr,
+                                                 const int* __restrict__ kit,
+                                                 cplx_t<R>* __restrict__ dq) {
     __shared__ double lds[3 * kT / 64];
     const int c = blockIdx.y;
     if (done[c]) return;
     const double2 a = alpha[c];
     const R ax = (R)a.x, ay = (R)a.y;
+    // simplified QMR: the step pending from the last iteration (none at k = 0)
+    const bool smooth = qmr && kit[c] > 0;
+    const R qa = smooth ? (R)qmr[8 * c + 2] : (R)0;
+    const R qbx = smooth ? (R)qmr[8 * c + 3] : (R)0, qby = smooth ? (R)qmr[8 * c + 4] : (R)0;
     cplx_t<R>* rc = r + (int64_t)c * N;
     const cplx_t<R>* qc = q + (int64_t)c * N;
     double s[3] = {0.0, 0.0, 0.0};
@@ -160,11 +167,22 @@ __global__ __launch_bounds__(kT) void k_r_update(cplx_t<R>* __restrict__ r,
         rv.x -= ax * qv.x - ay * qv.y;
         rv.y -= ax * qv.y + ay * qv.x;
         rc[i] = rv;
-        if (x) {
+        if (x && !qmr) {
             const cplx_t<R> pv = p[(int64_t)c * N + i];
             cplx_t<R> xv = x[(int64_t)c * N + i];
             xv.x += ax * pv.x - ay * pv.y;
             xv.y += ax * pv.y + ay * pv.x;
+            x[(int64_t)c * N + i] = xv;
+        } else if (smooth) {
+            const cplx_t<R> pv = p[(int64_t)c * N + i];
+            cplx_t<R> dv = dq[(int64_t)c * N + i];
+            cplx_t<R> xv = x[(int64_t)c * N + i];
+            cplx_t<R> dn;
+            dn.x = qa * dv.x + qbx * pv.x - qby * pv.y;
+            dn.y = qa * dv.y + qbx * pv.y + qby * pv.x;
+            dq[(int64_t)c * N + i] = dn;
+            xv.x += dn.x;
+            xv.y += dn.y;
             x[(int64_t)c * N + i] = xv;
         }
         const double rx = rv.x, ry = rv.y;
@@ -434,6 +452,21 @@ __global__ __launch_bounds__(kT) void k_reduce_beta_single(const double2* __rest
         const double2 rho_new = make_double2(s[0], s[1]);
         const double snew = sqrt(s[2]);
         const double2 beta = cdiv(rho_new, st.rho[c]);
+        if (st.qmr) {
+            // simplified QMR (Freund-Nachtigal): theta = ||r_{k+1}|| / tau,
+            // c^2 = 1 / (1 + theta^2), tau <- tau theta c, and the smoothed step
+            // d_{k+1} = c^2 theta_k^2 d_k + c^2 alpha_k p_k (applied next iteration)
+            double* qs = st.qmr + 8 * c;
+            const double tau = qs[0];
+            const double th = (tau > 0.0) ? snew / tau : 0.0;
+            const double c2 = 1.0 / (1.0 + th * th);
+            const double2 al = st.alpha[c];
+            qs[2] = c2 * qs[1];
+            qs[3] = c2 * al.x;
+            qs[4] = c2 * al.y;
+            qs[0] = tau * th * sqrt(c2);
+            qs[1] = th * th;
+        }
         st.rho[c] = rho_new;
         st.beta[c] = beta;
         st.rnorm[c] = snew;
@@ -503,10 +536,47 @@ void launch_reduce_alpha(const double2* part, int nblk, IterState st, hipStream_
 template <typename R>
 void launch_r_update(cplx_t<R>* r, const cplx_t<R>* q, cplx_t<R>* p, cplx_t<R>* x,
                      double2* part_rr, double* part_nn, const IterState& st, int64_t N,
-                     hipStream_t s) {
+                     hipStream_t s, cplx_t<R>* d_qmr) {
     dim3 g(part_blocks(N), st.w);
     hipLaunchKernelGGL((k_r_update<R>), g, dim3(kT), 0, s, r, q, p, x, N, st.done, st.alpha,
-                       part_rr, part_nn);
+                       part_rr, part_nn, d_qmr ? st.qmr : nullptr, st.k, d_qmr);
+}
+
+// the last pending simplified-QMR step of each column (see k_reduce_beta_single)
+template <typename R>
+__global__ __launch_bounds__(kT) void k_qmr_flush(const cplx_t<R>* __restrict__ p_even,
+                                                  const cplx_t<R>* __restrict__ p_odd,
+                                                  cplx_t<R>* __restrict__ dq,
+                                                  cplx_t<R>* __restrict__ x, int64_t N,
+                                                  const double* __restrict__ qmr,
+                                                  const int* __restrict__ kit,
+                                                  const int* __restrict__ skip) {
+    const int c = blockIdx.y;
+    if ((skip && skip[c]) || kit[c] == 0) return;
+    const int kl = kit[c] - 1;  // the iteration whose direction the step uses
+    const cplx_t<R>* p = ((kl & 1) ? p_odd : p_even) + (int64_t)c * N;
+    const R qa = (R)qmr[8 * c + 2], qbx = (R)qmr[8 * c + 3], qby = (R)qmr[8 * c + 4];
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kT) {
+        const cplx_t<R> pv = p[i];
+        const cplx_t<R> dv = dq[(int64_t)c * N + i];
+        cplx_t<R> dn;
+        dn.x = qa * dv.x + qbx * pv.x - qby * pv.y;
+        dn.y = qa * dv.y + qbx * pv.y + qby * pv.x;
+        dq[(int64_t)c * N + i] = dn;
+        cplx_t<R> xv = x[(int64_t)c * N + i];
+        xv.x += dn.x;
+        xv.y += dn.y;
+        x[(int64_t)c * N + i] = xv;
+    }
+}
+
+template <typename R>
+void launch_qmr_flush(const cplx_t<R>* p_even, const cplx_t<R>* p_odd, cplx_t<R>* d_qmr,
+                      cplx_t<R>* x, int64_t N, const IterState& st, const int* skip,
+                      hipStream_t s) {
+    dim3 g(part_blocks(N), st.w);
+    hipLaunchKernelGGL((k_qmr_flush<R>), g, dim3(kT), 0, s, p_even, p_odd, d_qmr, x, N, st.qmr,
+                       st.k, skip);
 }
 
 void launch_reduce_beta_multishift(const double2* part_rr, const double* part_nn, int nblk,
@@ -537,7 +607,10 @@ void launch_store_rows(const cplx_t<R>* r, int64_t N, int w, const int* rows, in
     template void launch_dot_pq<R>(const cplx_t<R>*, const cplx_t<R>*, double2*,               \
                                    const IterState&, int64_t, hipStream_t);                     \
     template void launch_r_update<R>(cplx_t<R>*, const cplx_t<R>*, cplx_t<R>*, cplx_t<R>*,      \
-                                     double2*, double*, const IterState&, int64_t, hipStream_t); \
+                                     double2*, double*, const IterState&, int64_t, hipStream_t,  \
+                                     cplx_t<R>*);                                                 \
+    template void launch_qmr_flush<R>(const cplx_t<R>*, const cplx_t<R>*, cplx_t<R>*, cplx_t<R>*, \
+                                      int64_t, const IterState&, const int*, hipStream_t);       \
     template void launch_store_rows<R>(const cplx_t<R>*, int64_t, int, const int*, int64_t, int, \
                                        double2*, int, const IterState&, int, hipStream_t,        \
                                        const int*);
@@ -618,6 +691,11 @@ __global__ __launch_bounds__(kT) void k_reduce_init(const double2* __restrict__ 
         st.alpha[c] = make_double2(0.0, 0.0);
         st.k[c] = 0;
         st.done[c] = sk ? 1 + NEGF_ITEM_CONVERGED : ((n == 0.0) ? 1 + NEGF_ITEM_CONVERGED : 0);
+        if (st.qmr) {
+            double* qs = st.qmr + 8 * c;
+            qs[0] = n;  // tau_0 = ||r_0||
+            qs[1] = qs[2] = qs[3] = qs[4] = 0.0;
+        }
         if (st.s_hist) st.s_hist[(int64_t)c * (st.max_iter + 1)] = n;
     }
     if (st.pih) {

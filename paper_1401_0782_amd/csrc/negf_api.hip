@@ -415,7 +415,7 @@ extern "C" negf_status negf_apply_operator(negf_op* op, int32_t precision, int32
 // shared pieces of the solver drivers
 // ---------------------------------------------------------------------------
 struct Defaults {
-    int precision, core, direction, max_iter, block_width, shift_group, max_refine;
+    int precision, core, solver, direction, max_iter, block_width, shift_group, max_refine;
     int col_begin, col_count;
     double tol;
 };
@@ -423,6 +423,7 @@ struct Defaults {
 static negf_status read_opts(const negf_opts* o, Defaults* d) {
     d->precision = o ? o->precision : NEGF_FP64;
     d->core = o ? o->core : NEGF_CORE_AUTO;
+    d->solver = o ? o->solver : NEGF_SOLVER_COCG;
     d->direction = o ? o->direction : NEGF_DIR_RL;
     d->tol = (o && o->tol > 0) ? o->tol : 1e-10;
     d->max_iter = (o && o->max_iter > 0) ? o->max_iter : 100000;
@@ -443,6 +444,14 @@ static negf_status read_opts(const negf_opts* o, Defaults* d) {
         set_error("unknown core %d", d->core);
         return NEGF_E_INVALID_ARG;
     }
+    if (d->solver != NEGF_SOLVER_COCG && d->solver != NEGF_SOLVER_QMR) {
+        set_error("unknown solver %d", d->solver);
+        return NEGF_E_INVALID_ARG;
+    }
+    if (d->solver == NEGF_SOLVER_QMR && d->core == NEGF_CORE_MULTISHIFT) {
+        set_error("the QMR solver runs in the per-energy core only");
+        return NEGF_E_INVALID_ARG;
+    }
     if (d->direction != NEGF_DIR_RL && d->direction != NEGF_DIR_LR) {
         set_error("unknown direction %d", d->direction);
         return NEGF_E_INVALID_ARG;
@@ -455,7 +464,7 @@ static negf_status read_opts(const negf_opts* o, Defaults* d) {
 }
 
 static negf_status make_state(negf_op* op, int w, int ng, int max_iter, double tol, bool hist,
-                              IterState* st, int chunk = 0) {
+                              IterState* st, int chunk = 0, bool qmr = false) {
     // one allocation carved into the state arrays
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
@@ -472,6 +481,7 @@ static negf_status make_state(negf_op* op, int w, int ng, int max_iter, double t
     const size_t o_sc = ng ? take((size_t)w * ng * sizeof(int)) : 0;
     const size_t o_sr = ng ? take((size_t)w * ng * sizeof(double)) : 0;
     const size_t o_rc = (ng && chunk) ? take((size_t)w * chunk * 3 * ng * sizeof(double2)) : 0;
+    const size_t o_qm = qmr ? take((size_t)w * 8 * sizeof(double)) : 0;
     unsigned char* base = nullptr;
     CHK(ws(op, WS_STATE, off, &base));
     st->w = w;
@@ -495,6 +505,7 @@ static negf_status make_state(negf_op* op, int w, int ng, int max_iter, double t
     st->sres = ng ? (double*)(base + o_sr) : nullptr;
     st->rec = (ng && chunk) ? (double2*)(base + o_rc) : nullptr;
     st->chunk = chunk;
+    st->qmr = qmr ? (double*)(base + o_qm) : nullptr;
     return NEGF_OK;
 }
 
@@ -928,8 +939,11 @@ static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, c
     double* bn64 = misc + w;       // [w] ||b||
     double* resid = misc + 2 * w;  // [w]
     int* odone = (int*)(misc + 3 * w);
+    const bool qmr = d.solver == NEGF_SOLVER_QMR;
+    cplx_t<R>* dq = nullptr;  // smoothed step of the simplified QMR iterate
+    if (qmr) CHK(ws(op, WS_QMRD, (size_t)w * N, &dq));
     IterState st;
-    CHK(make_state(op, w, 0, d.max_iter, d.tol, false, &st));
+    CHK(make_state(op, w, 0, d.max_iter, d.tol, false, &st, 0, qmr));
 
     HIPCHK(hipMemcpyAsync(shift, item_e, w * sizeof(double), hipMemcpyHostToDevice, s));
     if (cols) {
@@ -967,6 +981,7 @@ static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, c
             if (!h_odone[c]) ++refine[c];
         // inner solve A d = r64 / ||r64|| in precision R
         launch_scale_convert<R>(r64, r, dsol, N, w, odone, nu, s);
+        if (qmr) HIPCHK(hipMemsetAsync(dq, 0, (size_t)w * N * sizeof(cplx_t<R>), s));
         launch_norms<R>(r, N, w, odone, part, part_nn, s);
         launch_reduce_init(part, part_nn, nblk, st, odone, s);
         int k_host = 0;
@@ -982,7 +997,9 @@ static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, c
                                          part_f, kbc, s, e0, e1);
                     launch_reduce_alpha(part_f, nblk_f, st, s, op->kb.n_proj ? kbc : nullptr,
                                         op->kb.e, op->kb.n_proj);
-                    launch_r_update<R>(r, q, pout, dsol, part, part_nn, st, N, s);
+                    // COCG: x += alpha p_k; QMR: the pending smoothed step from p_{k-1}
+                    launch_r_update<R>(r, q, qmr ? pin : pout, dsol, part, part_nn, st, N, s,
+                                       qmr ? dq : nullptr);
                     launch_reduce_beta_single(part, part_nn, nblk, st, inner_tol, s);
                 }
                 return NEGF_OK;
@@ -1007,6 +1024,8 @@ static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, c
             }
         if (tm->on)
             tm->bytes += 4.0 * sizeof(cplx_t<R>) * (double)N * (double)col_iters + 8.0 * N * k_host;
+        // QMR: the last step is still pending; p_k sits in p2 for even k, in p for odd k
+        if (qmr) launch_qmr_flush<R>(p2, p, dq, dsol, N, st, odone, s);
         launch_accumulate<R>(x64, dsol, N, w, odone, nu, s);
     }
     for (int c = 0; c < w; ++c) {
@@ -1088,6 +1107,7 @@ static negf_status check_energies(int n_e, const double* e) {
 
 static int pick_core(const Defaults& d) {
     if (d.core != NEGF_CORE_AUTO) return d.core;
+    if (d.solver == NEGF_SOLVER_QMR) return NEGF_CORE_PER_ENERGY;
     return d.precision == NEGF_FP64 ? NEGF_CORE_MULTISHIFT : NEGF_CORE_PER_ENERGY;
 }
 

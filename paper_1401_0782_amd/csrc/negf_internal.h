@@ -103,7 +103,7 @@ enum WorkSlot {
     WS_R = 0, WS_P, WS_Q, WS_X, WS_B, WS_R64, WS_X64, WS_Q64,
     WS_PART, WS_PART2, WS_PART3, WS_KBC, WS_SHIFT, WS_COLJ,
     WS_STATE, WS_HIST, WS_PI, WS_GAMMA, WS_TRI, WS_TPART, WS_TCOL, WS_ROWS,
-    WS_ROWW, WS_RING, WS_XS, WS_PS, WS_COEF, WS_MISC, WS_SINK, WS_SLOTS, WS_COUNT
+    WS_ROWW, WS_RING, WS_XS, WS_PS, WS_COEF, WS_MISC, WS_SINK, WS_SLOTS, WS_QMRD, WS_COUNT
 };
 negf_status ws_get(negf_op* op, int slot, size_t bytes, void** out);
 
@@ -141,6 +141,9 @@ struct IterState {
     // rec[((c*chunk + k%chunk)*3 + t)*ng + g], t = 0: 1/pi_k, 1: alpha^sigma_k, 2: beta^sigma_k
     double2* rec = nullptr;
     int chunk = 0;
+    // simplified QMR smoothing (null for COCG): [w][8] = tau, theta^2 of the last
+    // step, and the pending iterate step d = a d + b p (a, b.re, b.im)
+    double* qmr = nullptr;
     int* running = nullptr;    // [1] count of running columns after a step
     double tol = 1e-10;
 };
@@ -169,10 +172,18 @@ void launch_update_ms(cplx_t<R>* r, const cplx_t<R>* q, int64_t N, const IterSta
                       const double2* part_f, int nblk_f, const negf_op* op, const double2* kbc,
                       double2* ring, int ring_len, int64_t row0, int n_rows, double2* part_rr,
                       double* part_nn, hipStream_t s);
+// r -= alpha q; x += alpha p (COCG), or with st.qmr the pending smoothed step
+// d = a d + b p, x += d, where p is then the previous direction
 template <typename R>
 void launch_r_update(cplx_t<R>* r, const cplx_t<R>* q, cplx_t<R>* p_or_null, cplx_t<R>* x_or_null,
                      double2* part_rr, double* part_nn, const IterState& st, int64_t N,
-                     hipStream_t s);
+                     hipStream_t s, cplx_t<R>* d_qmr = nullptr);
+// the last pending QMR step of every column: d = a d + b p_K, x += d, with
+// p_K in p_even (K even) or p_odd (K odd), K = k - 1
+template <typename R>
+void launch_qmr_flush(const cplx_t<R>* p_even, const cplx_t<R>* p_odd, cplx_t<R>* d_qmr,
+                      cplx_t<R>* x, int64_t N, const IterState& st, const int* skip,
+                      hipStream_t s);
 void launch_reduce_beta_multishift(const double2* part_rr, const double* part_nn, int nblk,
                                    IterState st, hipStream_t s);
 void launch_reduce_beta_single(const double2* part_rr, const double* part_nn, int nblk,

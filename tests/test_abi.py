@@ -152,3 +152,14 @@ def test_spectral_rejects_null_operator():
     e = np.array([0.3])
     assert lib.negf_spectral_transmission(None, 1, None, None, 1.0, 1, e.ctypes.data,
                                           None) == _abi.NEGF_E_INVALID_ARG
+
+
+def test_opts_layout_matches_header():
+    """The ctypes mirror of negf_opts has the header's field order."""
+    from paper_1401_0782_amd import _abi
+
+    text = (ROOT / "include" / "negf.h").read_text()
+    body = re.search(r"typedef struct \{((?:(?!typedef).)*?)\} negf_opts;", text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"\b(int32_t|double|void\*)\s+([a-z_]+);", body)
+    assert [f[1] for f in fields] == [f[0] for f in _abi.negf_opts._fields_]
