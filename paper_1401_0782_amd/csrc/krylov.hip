@@ -330,8 +330,11 @@ __global__ __launch_bounds__(kT) void k_update_ms(
     const int k = st.k[c];
     cplx_t<R>* rc = r + (int64_t)c * N;
     const cplx_t<R>* qc = q + (int64_t)c * N;
-    // each work-group owns one contiguous stretch; U loads per lane in flight
-    constexpr int U = 4;
+    // each work-group owns one contiguous stretch, U elements per lane per
+    // step with the next step's loads in flight; U = 2 measured fastest (on
+    // the 32x32x192 wire the stretch then takes two steps, and the second
+    // step's loads overlap the first's arithmetic)
+    constexpr int U = 2;
     const int64_t span = ((N + gridDim.x - 1) / gridDim.x + kT * U - 1) / (kT * U) * (kT * U);
     const int64_t i0 = (int64_t)blockIdx.x * span;
     const int64_t i1 = (i0 + span < N) ? i0 + span : N;

@@ -659,7 +659,10 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
                                         int64_t* total_iters, hipStream_t s, MatvecTimer* tm) {
     const int64_t N = op->N;
     const int nblk = part_blocks(N);
-    const int nblk_f = fused_partials(op, w);
+    // the stencil's z-chunking follows the number of running columns (finer
+    // chunks keep the CUs busy when few columns remain); partials are sized for
+    // the finest
+    const int nblk_f_max = fused_partials(op, 1);
     const int ch = kShiftChunk, ring_len = 2 * kShiftChunk;
     if (n_src < w || (n_src > w && (!cols || out.d_out))) {
         set_error("internal: column streaming needs unit right-hand sides in transmission mode");
@@ -674,7 +677,7 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
     CHK(ws(op, WS_X, (size_t)w * N, &p2));
     CHK(ws(op, WS_PART, (size_t)w * nblk, &part));
     CHK(ws(op, WS_PART2, (size_t)w * nblk, &part_nn));
-    CHK(ws(op, WS_PART3, (size_t)w * nblk_f, &part_f));
+    CHK(ws(op, WS_PART3, (size_t)w * nblk_f_max, &part_f));
     CHK(ws(op, WS_KBC, (size_t)w * std::max(1, op->kb.n_proj), &kbc));
     CHK(ws(op, WS_SHIFT, (size_t)w, &shift));
     CHK(ws(op, WS_COLJ, (size_t)w, &d_cols));
@@ -742,10 +745,15 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
     int launches = 0;
     ChunkGraph cg;
     const bool use_graph = graphs_enabled();
+    int running = w;  // columns still iterating at the chunk start
     while (true) {
         // a streaming block runs whole chunks (each column stops at its own
         // max_iter); a single block stops at max_iter
         const int steps = (n_src > w) ? ch : std::min(ch, d.max_iter - launches);
+        // the z-chunking for the running columns; the graph holds the full-width
+        // shape, narrower chunks run eagerly
+        const int w_geom = std::max(1, running);
+        const int nblk_f = fused_partials(op, w_geom);
         HIPCHK(hipMemcpyAsync(kstart, st.k, w * sizeof(int), hipMemcpyDeviceToDevice, s));
         auto issue = [&]() -> negf_status {
             for (int it = 0; it < steps; ++it) {
@@ -756,7 +764,7 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
                 hipEvent_t e0, e1;
                 CHK(tm->next(&e0, &e1));
                 launch_cocg_apply<double>(op, r, pin, pout, q, w, shift, st.done, st.k, st.beta,
-                                          part_f, kbc, s, e0, e1, !fused_update);
+                                          part_f, kbc, s, e0, e1, !fused_update, w_geom);
                 if (fused_update) {
                     // alpha, projector term, r update and kept rows in one launch
                     launch_update_ms<double>(r, q, N, st, part_f, nblk_f, op, kbc, ring, ring_len,
@@ -772,7 +780,7 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
             }
             return NEGF_OK;
         };
-        CHK(run_chunk(cg, use_graph && steps == ch, s, tm, issue));
+        CHK(run_chunk(cg, use_graph && steps == ch && w_geom == w, s, tm, issue));
         // fold the chunk's iterations into X and P of every energy
         launch_chunk_coef(st, kstart, cx, cp, xi_a, carry, active, s);
         launch_gemm_xp(ring, ring_len, w, n_rows, kstart, st, cx, cp, xi_a, active, X, P, s);
@@ -854,7 +862,12 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
             HIPCHK(hipGetLastError());
         }
         bool busy = false;
-        for (int c = 0; c < w; ++c) busy = busy || slot_src[c] >= 0;
+        running = 0;
+        for (int c = 0; c < w; ++c) {
+            busy = busy || slot_src[c] >= 0;
+            // restarted slots run; live ones run unless their column is done
+            running += (slot_src[c] >= 0 && (h_mask[c] || h_done[c] == 0)) ? 1 : 0;
+        }
         if (!busy) break;
     }
     if (tm->on) {

@@ -163,7 +163,10 @@ template <typename R>
 void launch_cocg_apply(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin,
                        cplx_t<R>* pout, cplx_t<R>* q, int w, const double* shift, const int* skip,
                        const int* kit, const double2* beta, double2* part, double2* d_kbc,
-                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, bool kb_scatter = true);
+                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, bool kb_scatter = true,
+                       int w_geom = 0);
+// partials per column of the fused kernel when its z-chunking is chosen for w
+// running columns (more chunks per column for fewer columns)
 int fused_partials(const negf_op* op, int w);
 // multi-shift alpha + projector term + r update + kept-row store in one launch
 // (krylov.hip); ring == null skips the row store

@@ -698,11 +698,12 @@ FusedGeom fused_geom(const negf_op* op, int w) {
     return g;
 }
 
+// w columns in the grid; the z-chunking is chosen for w_geom running columns
 template <int RAD, typename R, bool FUSED>
 void fused_launch(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin, cplx_t<R>* pout,
-                  cplx_t<R>* y, int w, const double* shift, const int* skip, const int* kit,
-                  const double2* beta, double2* part, hipStream_t s) {
-    const FusedGeom g = fused_geom<RAD, R>(op, w);
+                  cplx_t<R>* y, int w, int w_geom, const double* shift, const int* skip,
+                  const int* kit, const double2* beta, double2* part, hipStream_t s) {
+    const FusedGeom g = fused_geom<RAD, R>(op, w_geom);
     Coef<R> cf;
     for (int m = 0; m < 7; ++m) cf.a[m] = (R)op->coef.a[m];
     dim3 grid(g.n_ytiles * g.n_z, w);
@@ -762,15 +763,17 @@ template <typename R>
 void launch_cocg_apply(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin,
                        cplx_t<R>* pout, cplx_t<R>* q, int w, const double* shift, const int* skip,
                        const int* kit, const double2* beta, double2* part, double2* d_kbc,
-                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, bool kb_scatter) {
+                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, bool kb_scatter,
+                       int w_geom) {
     if (ev0) (void)hipEventRecord(ev0, s);
+    const int wg = w_geom > 0 ? w_geom : w;
     switch (op->R) {
-        case 1: fused_launch<1, R, true>(op, r, pin, pout, q, w, shift, skip, kit, beta, part, s); break;
-        case 2: fused_launch<2, R, true>(op, r, pin, pout, q, w, shift, skip, kit, beta, part, s); break;
-        case 3: fused_launch<3, R, true>(op, r, pin, pout, q, w, shift, skip, kit, beta, part, s); break;
-        case 4: fused_launch<4, R, true>(op, r, pin, pout, q, w, shift, skip, kit, beta, part, s); break;
-        case 5: fused_launch<5, R, true>(op, r, pin, pout, q, w, shift, skip, kit, beta, part, s); break;
-        default: fused_launch<6, R, true>(op, r, pin, pout, q, w, shift, skip, kit, beta, part, s); break;
+        case 1: fused_launch<1, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s); break;
+        case 2: fused_launch<2, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s); break;
+        case 3: fused_launch<3, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s); break;
+        case 4: fused_launch<4, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s); break;
+        case 5: fused_launch<5, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s); break;
+        default: fused_launch<6, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s); break;
     }
     if (ev1) (void)hipEventRecord(ev1, s);
     if (op->kb.n_proj > 0) {
@@ -789,8 +792,8 @@ void launch_cocg_apply(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* p
 template void launch_cocg_apply<double>(const negf_op*, const double2*, const double2*, double2*,
                                         double2*, int, const double*, const int*, const int*,
                                         const double2*, double2*, double2*, hipStream_t,
-                                        hipEvent_t, hipEvent_t, bool);
+                                        hipEvent_t, hipEvent_t, bool, int);
 template void launch_cocg_apply<float>(const negf_op*, const float2*, const float2*, float2*,
                                        float2*, int, const double*, const int*, const int*,
                                        const double2*, double2*, double2*, hipStream_t,
-                                       hipEvent_t, hipEvent_t, bool);
+                                       hipEvent_t, hipEvent_t, bool, int);
