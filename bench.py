@@ -34,9 +34,13 @@ COUNTERS = ROOT / "profiles" / "stencil_wire32x32x192_counters.txt"
 KERNEL_SRC = ROOT / "paper_1401_0782_amd" / "csrc" / "stencil.hip"
 
 
-def _traffic_from_profile():
+KERNELS = {1: "k_cocg_plane<6,double,true>", 0: "k_cocg_apply<6,double,1024,true>"}
+
+
+def _traffic_from_profile(kernel):
     """HBM bytes per launch of the fused stencil kernel from the committed
-    rocprofv3 counter summary, or None if missing or taken on other source."""
+    rocprofv3 counter summary, or None if missing, taken on other source or on
+    the other stencil kernel."""
     if not COUNTERS.exists():
         return None, None
     fields = {}
@@ -47,6 +51,8 @@ def _traffic_from_profile():
     src_hash = hashlib.sha256(KERNEL_SRC.read_bytes()).hexdigest()[:16]
     if fields.get("stencil_src_sha256_16") != src_hash:
         return None, "counters predate the current stencil source"
+    if fields.get("kernel") != kernel:
+        return None, f"counters were taken on {fields.get('kernel')}, this run used {kernel}"
     try:
         # measured with every column of the block active; per-launch traffic of
         # the timed run scales with its (smaller) average active-column count
@@ -89,10 +95,40 @@ def _oracle_worker(args):
     return n[0], time.perf_counter() - t0
 
 
-# BiCGSTAB iterations the oracle needs for one item of this workload at the
-# top energy (0.8 Ha), measured once by running its iterative route to a true
-# relative residual of 1e-12 on column 0 of the right absorbing region.
-ORACLE_ITERS_PER_SOLVE = None  # filled from profiles/oracle_wire32x32x192_iters.txt
+def _oracle_to_completion(e_index):
+    """One process: the oracle's BiCGSTAB on column 0 of the right absorbing
+    region at energy index e_index, run to completion; returns a record."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+    import numpy as np
+    import scipy.sparse.linalg as spla
+
+    import oracle as O
+    from workloads import make_wire, rhs_columns
+
+    w = make_wire(2)
+    j = int(rhs_columns(w)[0])
+    E = float(w.energies[e_index])
+    A = O.operator_A(w, E).tocsr()
+    b = np.zeros(w.N, complex)
+    b[j] = 1.0
+    n = [0]
+
+    def cb(_x):
+        n[0] += 1
+
+    t0 = time.perf_counter()
+    x, info = spla.bicgstab(A, b, rtol=1e-13, atol=0.0, maxiter=300000, callback=cb)
+    res = float(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
+    return {"e_index": e_index, "energy": E, "iters": n[0], "info": int(info),
+            "seconds": time.perf_counter() - t0, "true_res": res}
+
+
+def measure_oracle_iterations(e_indices):
+    """BiCGSTAB iterations per solve of the oracle at sampled energies (one
+    process each; about an hour of CPU time for the slow energies)."""
+    with mp.get_context("spawn").Pool(len(e_indices)) as pool:
+        for rec in pool.imap(_oracle_to_completion, e_indices):
+            print(json.dumps(rec), flush=True)
 
 
 def _oracle_iters_per_solve():
@@ -125,9 +161,10 @@ def cpu_baseline(seconds: float):
         "sample": (f"{n_proc} worker processes (1 BLAS thread each), each running the oracle's "
                    f"iterative route (scipy BiCGSTAB, FP64, sparse A(E)) on its own column at "
                    f"E=0.8 Ha of the same wire for {seconds:.0f} s; measured "
-                   f"{it_rate:.1f} iterations/s in total, divided by the "
-                   f"{per_solve} iterations one such solve needs to reach a true residual of "
-                   f"1e-12 (measured to completion once, profiles/oracle_wire32x32x192_iters.txt)"),
+                   f"{it_rate:.1f} iterations/s in total, divided by the mean of "
+                   f"{per_solve} iterations per solve over the energy grid (solves run to a true "
+                   f"residual of 1e-12 at six sampled energies, "
+                   f"profiles/oracle_wire32x32x192_iters.txt)"),
     }
 
 
@@ -143,7 +180,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device copy (counter calibration under rocprofv3)")
+    ap.add_argument("--launch-shape", type=str, default=None, metavar="WG_TARGET,PLANE",
+                    help="fix the stencil launch shape instead of tuning it (profiler runs)")
+    ap.add_argument("--oracle-iterations", type=str, default=None, metavar="E_IDX,...",
+                    help="CPU only: run the oracle's BiCGSTAB to completion at these energy "
+                         "indices and print the iteration counts (the CPU baseline's scale)")
     args = ap.parse_args()
+    if args.oracle_iterations:
+        measure_oracle_iterations([int(v) for v in args.oracle_iterations.split(",")])
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -171,8 +216,16 @@ def main():
         torch.cuda.synchronize()
 
     # launch shape (z-chunking, stencil kernel) for this block width, picked once
-    # by the library's autotuner before any timing
-    tuned = P.negf_tune(op, wire.energies, block_width=args.block)
+    # by the library's autotuner before any timing (or fixed for profiler runs,
+    # whose timing would mislead the tuner)
+    if args.launch_shape:
+        tgt, plane = (int(v) for v in args.launch_shape.split(","))
+        P.negf_set_launch_shape(op, args.block, tgt, plane)
+        tuned = {"block_width": args.block, "wg_target": tgt, "plane_kernel": plane}
+    else:
+        tuned = P.negf_tune(op, wire.energies, block_width=args.block)
+    plane_fits = wire.nx * wire.ny <= 1024 and (wire.nx * wire.ny) % 64 == 0
+    kernel = KERNELS[1 if (tuned["plane_kernel"] != 0 and plane_fits) else 0]
     print(f"tuned launch shape: block {tuned['block_width']}, stencil work-groups "
           f"{tuned['wg_target']}, whole-plane kernel {tuned['plane_kernel']}",
           file=sys.stderr, flush=True)
@@ -211,7 +264,7 @@ def main():
     solves = args.steps * args.block * n_e
     value = solves / elapsed
     achieved = mv_b / mv_s / 1e9 if mv_s > 0 else None
-    ratio, why = _traffic_from_profile()
+    ratio, why = _traffic_from_profile(kernel)
     traffic = ratio * mv_b / max(1, mv_n) if ratio else None
     roofline = {
         "bound": "hbm",
@@ -220,7 +273,7 @@ def main():
         "unit": "GB/s",
         "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
         "traffic": traffic,  # HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)
-        "kernel": "k_cocg_plane<6,double,true> (fused p = r + beta p, stencil + potential + CAP apply, p^T q partials)",
+        "kernel": kernel + " (fused p = r + beta p, stencil + potential + CAP apply, p^T q partials)",
         "launches": mv_n,
         "avg_launch_us": 1e6 * mv_s / max(1, mv_n),
         "bytes_per_launch": mv_b / max(1, mv_n),
