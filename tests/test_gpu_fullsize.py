@@ -84,3 +84,30 @@ def test_oracle_samples(op2, wire2):
             print(f"col {smp['col']} E {smp['energy']:.4f}: t {t:.6e} oracle {smp['t_col']:.6e} "
                   f"|dt| {err:.2e}", flush=True)
             assert err <= 6e-13, (smp, t)
+
+
+def test_largest_wire_optical_theorem():
+    """The 64x64x256 R=6 wire with 80 atoms' projectors (N = 1,048,576, the
+    largest workload), 8 source columns x 16 energies (energies[::64]) through
+    the multi-shift core: the per-column optical theorem on the CAP rows."""
+    import paper_1401_0782_amd as P
+
+    w = make_wire(5)
+    op = P.operator_from_wire(w)
+    per = w.nx * w.ny
+    cols = rhs_columns(w)[::10240][:8]
+    L = left_support(w)
+    Rr = rhs_columns(w)
+    rows = np.concatenate([L, Rr]).astype(np.int32)
+    W = np.concatenate([np.repeat(w.cap_left, per)[L], np.repeat(w.cap_right, per)[Rr]])
+    E = w.energies[::64]
+    out, st = P.negf_solve_columns(op, E, rhs_idx=cols, row_idx=rows, tol=1e-10,
+                                   core=P.NEGF_CORE_MULTISHIFT, block_width=8)
+    assert np.all(st == 0)
+    pos = {int(r): k for k, r in enumerate(rows)}
+    jj = np.array([pos[int(j)] for j in cols])
+    g_jj = out[:, np.arange(len(cols)), jj]
+    lhs = np.einsum("ecr,r->ec", np.abs(out) ** 2, W)
+    rel = np.abs(lhs + g_jj.imag) / np.abs(g_jj)
+    assert rel.max() < 1e-7, rel.max()
+    op.close()

@@ -120,3 +120,34 @@ def test_solve_columns_match_oracle(gpu_lib):
             # a relative residual tol bounds it by ||A^-1|| tol
             err = (np.abs(out[e].T - G) / np.abs(Gfull).max(axis=0)).max()
             assert err < 1e-9, (core, e, err)
+
+
+def test_chain_one_point_planes(gpu_lib):
+    """The degenerate 1 x 1 x nz grid (a chain; planes of one point, the
+    row-tiled stencil kernel) with long CAPs: both cores against the oracle."""
+    import paper_1401_0782_amd as P
+
+    w = make_custom(1, 1, 200, 0.5, 2, 80, np.linspace(0.3, 3.0, 6), w0=0.5)
+    op = _op(w)
+    T_ref = O.transmission(w, method="dense")
+    for core in (P.NEGF_CORE_MULTISHIFT, P.NEGF_CORE_PER_ENERGY):
+        T = P.negf_transmission(op, w.energies, tol=1e-12, core=core)
+        assert np.max(np.abs(T - T_ref)) <= 1e-8, (core, T, T_ref)
+
+
+def test_invalid_calls_rejected(gpu_lib):
+    """Empty energy lists, out-of-range shards and null outputs are errors,
+    not launches."""
+    import paper_1401_0782_amd as P
+
+    w = make_wire(1)
+    op = _op(w)
+    with pytest.raises(P.NegfError):
+        P.negf_transmission(op, np.zeros(0))
+    with pytest.raises(P.NegfError):
+        P.negf_transmission(op, w.energies, col_begin=380, col_count=10)
+    with pytest.raises(P.NegfError):
+        P.negf_transmission(op, np.array([0.3, np.nan]))
+    # the operator still works afterwards
+    T = P.negf_transmission(op, w.energies, tol=1e-12)
+    assert np.max(np.abs(T - O.transmission(w, method="dense"))) <= 1e-8
