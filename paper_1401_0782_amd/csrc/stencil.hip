@@ -16,6 +16,10 @@
 // the tiles of one column are issued consecutively).
 #include <algorithm>
 
+#include <mutex>
+#include <set>
+#include <utility>
+
 #include "negf_internal.h"
 
 namespace {
@@ -698,6 +702,19 @@ FusedGeom fused_geom(const negf_op* op, int w) {
     return g;
 }
 
+// gfx950 has 160 KB of LDS per CU; dynamic allocations above 64 KB must be
+// opted in, once per kernel and device (host threads of a junction batch may
+// get here together)
+void allow_large_lds(const void* kernel) {
+    static std::mutex mu;
+    static std::set<std::pair<const void*, int>> done;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.insert({kernel, dev}).second)
+        (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
 // w columns in the grid; the z-chunking is chosen for w_geom running columns
 template <int RAD, typename R, bool FUSED>
 void fused_launch(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin, cplx_t<R>* pout,
@@ -708,34 +725,16 @@ void fused_launch(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin, c
     for (int m = 0; m < 7; ++m) cf.a[m] = (R)op->coef.a[m];
     dim3 grid(g.n_ytiles * g.n_z, w);
     if (g.whole_plane) {
-        if (g.lds > 65536) {
-            static bool done_plane = false;
-            if (!done_plane) {
-                (void)hipFuncSetAttribute((const void*)k_cocg_plane<RAD, R, FUSED>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-                done_plane = true;
-            }
-        }
+        if (g.lds > 65536) allow_large_lds((const void*)k_cocg_plane<RAD, R, FUSED>);
         hipLaunchKernelGGL((k_cocg_plane<RAD, R, FUSED>), grid, dim3(g.nt), g.lds, s, r, pin, pout,
                            y, reinterpret_cast<cplx_t<R>*>(op->d_sink), op->nx, op->ny, op->nz,
                            g.zchunk, cf, op->coef.a[0], op->d_v, op->d_wz, shift, skip, kit, beta,
                            part);
         return;
     }
-    if (g.lds > 65536) {
-        // gfx950 has 160 KB of LDS per CU; dynamic allocations above 64 KB must be opted in
-        static bool done256 = false, done1024 = false;
-        bool& done = (g.nt == 256) ? done256 : done1024;
-        if (!done) {
-            if (g.nt == 256)
-                (void)hipFuncSetAttribute((const void*)k_cocg_apply<RAD, R, 256, FUSED>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            else
-                (void)hipFuncSetAttribute((const void*)k_cocg_apply<RAD, R, 1024, FUSED>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            done = true;
-        }
-    }
+    if (g.lds > 65536)
+        allow_large_lds(g.nt == 256 ? (const void*)k_cocg_apply<RAD, R, 256, FUSED>
+                                    : (const void*)k_cocg_apply<RAD, R, 1024, FUSED>);
     if (g.nt == 256)
         hipLaunchKernelGGL((k_cocg_apply<RAD, R, 256, FUSED>), grid, dim3(256), g.lds, s, r, pin,
                            pout, y, op->nx, op->ny, op->nz, g.ty, g.n_ytiles, g.zchunk, cf,
