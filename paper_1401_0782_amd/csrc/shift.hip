@@ -180,8 +180,10 @@ __global__ __launch_bounds__(kT) void k_gemm_xp(const double2* __restrict__ ring
 // and holds D[4 i + l / 16][l % 16], i = 0..3.  A complex product takes four
 // real ones: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.  A work-group of four
 // waves owns 64 rows x 32 energies; each wave 32 rows x 16 energies as two
-// 16 x 16 blocks for X and two for P (eight accumulators), which keeps the
-// register count low enough for several work-groups per CU.
+// 16 x 16 blocks for X and two for P (eight accumulators). The launch bound
+// asks for four waves per SIMD (110 VGPRs, no spills): four work-groups per
+// CU hide the staging loads better than three (10.7 ms against 12.4 ms per
+// 128-iteration chunk on the 32x32x192 wire).
 typedef double d4_t __attribute__((ext_vector_type(4)));
 constexpr int MK = 16;   // chunk iterations staged per LDS pass
 constexpr int MTN = 32;  // energies per work-group
@@ -190,7 +192,7 @@ __device__ inline d4_t mfma4(double a, double b, d4_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-__global__ __launch_bounds__(kT) void k_gemm_xp_mfma(const double2* __restrict__ ring, int ring_len,
+__global__ __launch_bounds__(kT, 4) void k_gemm_xp_mfma(const double2* __restrict__ ring, int ring_len,
                                                      int w, int n_rows,
                                                      const int* __restrict__ kstart, IterState st,
                                                      const double2* __restrict__ cx,
