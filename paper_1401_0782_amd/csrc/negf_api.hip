@@ -186,6 +186,8 @@ static void free_op(negf_op* op) {
         return;
     }
     (void)hipSetDevice(op->device);
+    if (op->own_stream) (void)hipStreamSynchronize(op->own_stream);
+    if (op->side_stream) (void)hipStreamSynchronize(op->side_stream);
     void* ptrs[] = {op->d_v, op->d_wz, op->d_wl, op->d_wr, op->kb.off, op->kb.idx, op->kb.val,
                     op->kb.valf, op->kb.e, op->kb.pts, op->kb.pt_off, op->kb.pt_proj, op->kb.pt_val, op->kb.slot};
     for (void* p : ptrs)
@@ -193,6 +195,7 @@ static void free_op(negf_op* op) {
     for (auto& b : op->bufs)
         if (b.ptr) (void)hipFree(b.ptr);
     if (op->own_stream) (void)hipStreamDestroy(op->own_stream);
+    if (op->side_stream) (void)hipStreamDestroy(op->side_stream);
     delete op;
 }
 
@@ -331,6 +334,7 @@ static negf_status build_impl(const negf_grid* g, int32_t R, const double* v, co
     CHK(upload(&op->d_wl, capl, (size_t)g->nz));
     CHK(upload(&op->d_wr, capr, (size_t)g->nz));
     HIPCHK(hipStreamCreateWithFlags(&op->own_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&op->side_stream, hipStreamNonBlocking));
     op->bufs.resize(WS_COUNT);
     return NEGF_OK;
 }
@@ -663,7 +667,9 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
     // chunks keep the CUs busy when few columns remain); partials are sized for
     // the finest
     const int nblk_f_max = fused_partials(op, 1);
-    const int ch = kShiftChunk, ring_len = 2 * kShiftChunk;
+    // ring of 2c + 1 slots: while the GEMM of chunk j reads its c residuals,
+    // chunk j + 1 stores the next c + 1 without touching them
+    const int ch = kShiftChunk, ring_len = 2 * kShiftChunk + 1;
     if (n_src < w || (n_src > w && (!cols || out.d_out))) {
         set_error("internal: column streaming needs unit right-hand sides in transmission mode");
         return NEGF_E_INVALID_ARG;
@@ -693,12 +699,31 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
     double2* xi_a = coef + 2 * n_cxp;
     double2* carry = xi_a + 2 * (size_t)w * ng;
     int* active = (int*)(carry + (size_t)w * ng);
-    // per slot: iteration count at the chunk start, a slot mask, its T weight
+    // per slot: iteration count at the chunk start (two chunks' worth: the GEMM
+    // of one chunk overlaps the next), chunk length, slot masks
     int* slots;
-    CHK(ws(op, WS_SLOTS, 3 * (size_t)w, &slots));
-    int* kstart = slots;
-    int* d_mask = slots + w;
-    int* d_notmask = slots + 2 * w;
+    CHK(ws(op, WS_SLOTS, 5 * (size_t)w, &slots));
+    int* kstart_buf[2] = {slots, slots + w};
+    int* clen = slots + 2 * w;
+    int* d_mask = slots + 3 * w;
+    int* d_notmask = slots + 4 * w;
+    // the GEMM of chunk j runs on the side stream while chunk j + 1 iterates;
+    // ev_coef orders it after its coefficients, ev_gemm orders later users of
+    // X, P and the coefficient buffers after it
+    // (timed runs keep the GEMM on the main stream, so that every timed stencil
+    // launch has the device to itself)
+    hipStream_t side = tm->on ? s : op->side_stream;
+    hipEvent_t ev_coef = nullptr, ev_gemm = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&ev_coef, hipEventDisableTiming));
+    if (hipEventCreateWithFlags(&ev_gemm, hipEventDisableTiming) != hipSuccess) {
+        (void)hipEventDestroy(ev_coef);
+        HIPCHK(hipErrorOutOfMemory);
+    }
+    struct EventGuard {
+        hipEvent_t a, b;
+        ~EventGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+    } ev_guard{ev_coef, ev_gemm};
+    bool gemm_pending = false;
     IterState st;
     CHK(make_state(op, w, ng, d.max_iter, d.tol, true, &st, ch));
     // fused update (alpha, projector term, r, kept rows) needs contiguous kept rows
@@ -754,6 +779,7 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
         // shape, narrower chunks run eagerly
         const int w_geom = std::max(1, running);
         const int nblk_f = fused_partials(op, w_geom);
+        int* kstart = kstart_buf[(launches / ch) & 1];
         HIPCHK(hipMemcpyAsync(kstart, st.k, w * sizeof(int), hipMemcpyDeviceToDevice, s));
         auto issue = [&]() -> negf_status {
             for (int it = 0; it < steps; ++it) {
@@ -781,9 +807,17 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
             return NEGF_OK;
         };
         CHK(run_chunk(cg, use_graph && steps == ch && w_geom == w, s, tm, issue));
-        // fold the chunk's iterations into X and P of every energy
-        launch_chunk_coef(st, kstart, cx, cp, xi_a, carry, active, s);
-        launch_gemm_xp(ring, ring_len, w, n_rows, kstart, st, cx, cp, xi_a, active, X, P, s);
+        // fold the chunk's iterations into X and P of every energy: the
+        // coefficients here (after the previous GEMM has read its own), the GEMM
+        // on the side stream, overlapping the next chunk
+        if (gemm_pending) HIPCHK(hipStreamWaitEvent(s, ev_gemm, 0));
+        launch_chunk_coef(st, kstart, clen, cx, cp, xi_a, carry, active, s);
+        HIPCHK(hipEventRecord(ev_coef, s));
+        HIPCHK(hipStreamWaitEvent(side, ev_coef, 0));
+        launch_gemm_xp(ring, ring_len, w, n_rows, kstart, clen, st, cx, cp, xi_a, active, X, P,
+                       side);
+        HIPCHK(hipEventRecord(ev_gemm, side));
+        gemm_pending = true;
         HIPCHK(hipGetLastError());
         launches += steps;
         HIPCHK(hipMemcpyAsync(h_done.data(), st.done, w * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -797,6 +831,8 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
             h_mask[c] = (slot_src[c] >= 0 && (h_done[c] != 0 || stop)) ? 1 : 0;
             n_fin += h_mask[c];
         }
+        // finished slots read X and restarted ones clear it: the GEMM first
+        if (n_fin > 0) HIPCHK(hipStreamWaitEvent(s, ev_gemm, 0));
         if (n_fin > 0 && out.d_out) {
             // column mode: X stays in place and is copied out at the end
             for (int c = 0; c < w; ++c)
@@ -845,6 +881,7 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
             h_notmask[c] = 1 - h_mask[c];
         }
         if (n_new > 0) {
+            HIPCHK(hipStreamWaitEvent(s, ev_gemm, 0));  // X, P, carry are rewritten below
             HIPCHK(hipMemcpyAsync(d_mask, h_mask.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
             HIPCHK(hipMemcpyAsync(d_notmask, h_notmask.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
             HIPCHK(hipMemcpyAsync(d_cols, h_colsel.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
@@ -874,6 +911,7 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
         // per column-iteration: r, p_{k-1} read, p_k, q written; V once per launch
         tm->bytes += 4.0 * sizeof(double2) * (double)N * (double)col_iters + 8.0 * N * launches;
     }
+    if (gemm_pending) HIPCHK(hipStreamWaitEvent(s, ev_gemm, 0));
     if (out.d_out) {
         // column mode: every slot is still live here (n_src == w)
         for (int c = 0; c < w; ++c) {
@@ -1541,6 +1579,7 @@ extern "C" negf_status negf_transmission_grad(negf_op* op, const negf_opts* opts
 
 static void release_workspace(negf_op* op) {
     (void)hipStreamSynchronize(op->own_stream);
+    (void)hipStreamSynchronize(op->side_stream);
     for (auto& b : op->bufs) {
         if (b.ptr) (void)hipFree(b.ptr);
         b.ptr = nullptr;

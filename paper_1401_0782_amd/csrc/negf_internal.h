@@ -82,6 +82,7 @@ struct negf_op {
     void* d_sink = nullptr;      // discard target of the whole-plane stencil kernel (workspace)
     DeviceKB kb;
     hipStream_t own_stream = nullptr;
+    hipStream_t side_stream = nullptr;  // the shift-accumulation GEMM, beside the iterations
     std::vector<Buffer> bufs;    // workspace, indexed by WorkSlot
     // launch shape (negf_tune); 0 / -1 = built-in choice
     int tuned_w = 0;             // source columns per multi-shift block
@@ -196,10 +197,12 @@ void launch_store_rows(const cplx_t<R>* r, int64_t N, int w, const int* rows, in
                        int n_rows, double2* ring, int ring_len, const IterState& st,
                        int slot_offset, hipStream_t s, const int* only = nullptr);
 // blocked multi-shift accumulation (shift.hip)
-// kstart[c]: the column's iteration count at the start of the chunk
-void launch_chunk_coef(const IterState& st, const int* kstart, double2* cx, double2* cp,
-                       double2* xi_a, double2* carry, int* active, hipStream_t s);
+// kstart[c]: the column's iteration count at the start of the chunk; the
+// coefficient kernel writes each column's chunk length to clen for the GEMM
+void launch_chunk_coef(const IterState& st, const int* kstart, int* clen, double2* cx,
+                       double2* cp, double2* xi_a, double2* carry, int* active, hipStream_t s);
 void launch_gemm_xp(const double2* ring, int ring_len, int w, int n_rows, const int* kstart,
+                    const int* clen,
                     const IterState& st, const double2* cx, const double2* cp,
                     const double2* xi_a, const int* active, double2* X, double2* P,
                     hipStream_t s);

@@ -27,6 +27,7 @@ constexpr int kT = 256;
 // One thread per (column, energy): coefficients of the column's chunk
 // [kstart, kstart + cl) (kstart is a multiple of the chunk length).
 __global__ __launch_bounds__(kT) void k_chunk_coef(IterState st, const int* __restrict__ kstart,
+                                                   int* __restrict__ clen,
                                                    double2* __restrict__ cx,
                                                    double2* __restrict__ cp,
                                                    double2* __restrict__ xi_a,
@@ -37,6 +38,9 @@ __global__ __launch_bounds__(kT) void k_chunk_coef(IterState st, const int* __re
     const int ng = st.ng, ch = st.chunk;
     if (g >= ng) return;
     const int cl = max(0, min(ch, st.k[c] - kstart[c]));
+    // the chunk length for the GEMM, which may run while the next chunk
+    // already advances st.k
+    if (g == 0) clen[c] = cl;
     const int64_t o = (int64_t)c * ng + g;
     double2* CX = cx + (int64_t)c * ch * ng + g;
     double2* CP = cp + (int64_t)c * ch * ng + g;
@@ -76,7 +80,7 @@ __global__ __launch_bounds__(kT) void k_chunk_coef(IterState st, const int* __re
 constexpr int TM = 64, TN = 64, TK = 16;
 
 __global__ __launch_bounds__(kT) void k_gemm_xp(const double2* __restrict__ ring, int ring_len,
-                                                int w, int n_rows, const int* __restrict__ kstart,
+                                                int w, int n_rows, const int* __restrict__ kstart, const int* __restrict__ clen,
                                                 IterState st,
                                                 const double2* __restrict__ cx,
                                                 const double2* __restrict__ cp,
@@ -92,7 +96,7 @@ __global__ __launch_bounds__(kT) void k_gemm_xp(const double2* __restrict__ ring
     const int g0 = blockIdx.y * TN;
     const int ng = st.ng, ch = st.chunk;
     const int k0 = kstart[c];
-    const int cl = max(0, min(ch, st.k[c] - k0));
+    const int cl = clen[c];
     if (cl == 0) return;
     const int tid = threadIdx.x;
     if (tid == 0) any_active = 0;
@@ -194,7 +198,7 @@ __device__ inline d4_t mfma4(double a, double b, d4_t c) {
 
 __global__ __launch_bounds__(kT, 4) void k_gemm_xp_mfma(const double2* __restrict__ ring, int ring_len,
                                                      int w, int n_rows,
-                                                     const int* __restrict__ kstart, IterState st,
+                                                     const int* __restrict__ kstart, const int* __restrict__ clen, IterState st,
                                                      const double2* __restrict__ cx,
                                                      const double2* __restrict__ cp,
                                                      const double2* __restrict__ xi_a,
@@ -210,7 +214,7 @@ __global__ __launch_bounds__(kT, 4) void k_gemm_xp_mfma(const double2* __restric
     const int g0 = blockIdx.y * MTN;
     const int ng = st.ng, ch = st.chunk;
     const int k0 = kstart[c];
-    const int cl = max(0, min(ch, st.k[c] - k0));
+    const int cl = clen[c];
     if (cl == 0) return;
     const int tid = threadIdx.x;
     if (tid == 0) any_active = 0;
@@ -328,14 +332,15 @@ __global__ __launch_bounds__(kT) void k_copy_out(const double2* __restrict__ X, 
 
 }  // namespace
 
-void launch_chunk_coef(const IterState& st, const int* kstart, double2* cx, double2* cp,
-                       double2* xi_a, double2* carry, int* active, hipStream_t s) {
+void launch_chunk_coef(const IterState& st, const int* kstart, int* clen, double2* cx,
+                       double2* cp, double2* xi_a, double2* carry, int* active, hipStream_t s) {
     dim3 g((st.ng + kT - 1) / kT, st.w);
-    hipLaunchKernelGGL(k_chunk_coef, g, dim3(kT), 0, s, st, kstart, cx, cp, xi_a, carry, active);
+    hipLaunchKernelGGL(k_chunk_coef, g, dim3(kT), 0, s, st, kstart, clen, cx, cp, xi_a, carry,
+                       active);
 }
 
 void launch_gemm_xp(const double2* ring, int ring_len, int w, int n_rows, const int* kstart,
-                    const IterState& st, const double2* cx, const double2* cp,
+                    const int* clen, const IterState& st, const double2* cx, const double2* cp,
                     const double2* xi_a, const int* active, double2* X, double2* P,
                     hipStream_t s) {
     dim3 g((n_rows + TM - 1) / TM, (st.ng + TN - 1) / TN, w);
@@ -343,11 +348,12 @@ void launch_gemm_xp(const double2* ring, int ring_len, int w, int n_rows, const 
     const char* env = getenv("NEGF_GEMM_VALU");
     const bool valu = env && env[0] == '1';
     if (valu)
-        hipLaunchKernelGGL(k_gemm_xp, g, dim3(kT), 0, s, ring, ring_len, w, n_rows, kstart, st, cx,
-                           cp, xi_a, active, X, P);
+        hipLaunchKernelGGL(k_gemm_xp, g, dim3(kT), 0, s, ring, ring_len, w, n_rows, kstart, clen,
+                           st, cx, cp, xi_a, active, X, P);
     else
         hipLaunchKernelGGL(k_gemm_xp_mfma, dim3(g.x, (st.ng + MTN - 1) / MTN, w), dim3(kT), 0, s,
-                           ring, ring_len, w, n_rows, kstart, st, cx, cp, xi_a, active, X, P);
+                           ring, ring_len, w, n_rows, kstart, clen, st, cx, cp, xi_a, active, X,
+                           P);
 }
 
 void launch_t_from_x(const double2* X, int n_rows, int w, int ng, const double* row_w,
