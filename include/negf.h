@@ -129,9 +129,13 @@ typedef struct {
     int64_t total_iters;     /* out: sum of Krylov iterations over runs */
     int32_t n_not_converged; /* out */
     double seconds;          /* out: wall time of the device work */
-    int32_t time_matvec;     /* in: nonzero brackets every fused stencil launch with
-                                HIP events on the work stream */
-    double matvec_seconds;   /* out: summed duration of those launches */
+    int32_t time_matvec;     /* in: 0 off; 1 brackets every fused stencil launch with
+                                HIP events on the work stream (launched eagerly);
+                                n > 1: in the multi-shift core, the launches of
+                                every n-th chunk of 128 iterations are timed that
+                                way and the other chunks replay as graphs (the
+                                per-energy core times every launch) */
+    double matvec_seconds;   /* out: summed duration of the timed launches */
     int64_t matvec_launches; /* out: number of stencil launches timed */
     double matvec_bytes;     /* out: algorithmic HBM bytes of those launches: per
                                 active column r and p_{k-1} read, p_k and q written

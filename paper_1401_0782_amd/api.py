@@ -163,7 +163,8 @@ def negf_transmission(op: Operator, energies, n_cols: Optional[int] = None, chec
                       time_matvec=False, **opts):
     """T(E) (FP64) for the given energies.  n_cols (number of source columns
     in the shard, see col_begin/col_count) enables the per-item diagnostics;
-    time_matvec brackets the stencil launches with HIP events."""
+    time_matvec brackets the stencil launches with HIP events (an int n > 1
+    times every n-th chunk of the multi-shift core)."""
     energies = np.ascontiguousarray(energies, dtype=np.float64)
     n_e = energies.size
     T = np.zeros(n_e)
@@ -180,7 +181,7 @@ def negf_transmission(op: Operator, energies, n_cols: Optional[int] = None, chec
                     arrays[1].ctypes.data_as(C.POINTER(C.c_double)),
                     arrays[2].ctypes.data_as(C.POINTER(C.c_double)),
                     arrays[3].ctypes.data_as(C.POINTER(C.c_int32))]
-        d = _abi.negf_diag(*ptrs, 0, 0, 0.0, 1 if time_matvec else 0, 0.0, 0, 0.0)
+        d = _abi.negf_diag(*ptrs, 0, 0, 0.0, int(time_matvec), 0.0, 0, 0.0)
     st = _lib().negf_transmission(op.handle, C.byref(o), n_e, _ptr(energies), _ptr(T),
                                   C.byref(d) if d is not None else None)
     if check:

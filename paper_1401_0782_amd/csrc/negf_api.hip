@@ -517,14 +517,17 @@ static negf_status make_state(negf_op* op, int w, int ng, int max_iter, double t
 // pairs are recorded around each launch and summed at the drivers' sync points.
 struct MatvecTimer {
     bool on = false;
+    bool active = true;  // whether the launches being issued are timed
+    int period = 1;      // multi-shift core: time every period-th chunk
     std::vector<hipEvent_t> ev;
     int used = 0;
     double seconds = 0.0;
     int64_t launches = 0;
     double bytes = 0.0;
     static constexpr int kPool = 256;
-    negf_status init(bool enable) {
-        on = enable;
+    negf_status init(int every) {
+        on = every > 0;
+        period = std::max(1, every);
         if (!on) return NEGF_OK;
         ev.resize(2 * kPool);
         for (auto& e : ev) HIPCHK(hipEventCreate(&e));
@@ -533,7 +536,7 @@ struct MatvecTimer {
     // events for the next launch (null when off); flushes a full pool first
     negf_status next(hipEvent_t* a, hipEvent_t* b) {
         *a = *b = nullptr;
-        if (!on) return NEGF_OK;
+        if (!on || !active) return NEGF_OK;
         if (used == kPool) CHK(flush());
         *a = ev[2 * used];
         *b = ev[2 * used + 1];
@@ -595,7 +598,7 @@ template <typename F>
 static negf_status run_chunk(ChunkGraph& cg, bool use_graph, hipStream_t s, MatvecTimer* tm,
                              F issue) {
     // per-kernel HIP events cannot be timed inside a graph: timed runs go eagerly
-    if (tm->on) use_graph = false;
+    if (tm->on && tm->active) use_graph = false;
     if (use_graph && !cg.failed && !cg.exec) {
         CHK(tm->flush());
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
@@ -710,9 +713,7 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
     // the GEMM of chunk j runs on the side stream while chunk j + 1 iterates;
     // ev_coef orders it after its coefficients, ev_gemm orders later users of
     // X, P and the coefficient buffers after it
-    // (timed runs keep the GEMM on the main stream, so that every timed stencil
-    // launch has the device to itself)
-    hipStream_t side = tm->on ? s : op->side_stream;
+    hipStream_t side = op->side_stream;
     hipEvent_t ev_coef = nullptr, ev_gemm = nullptr;
     HIPCHK(hipEventCreateWithFlags(&ev_coef, hipEventDisableTiming));
     if (hipEventCreateWithFlags(&ev_gemm, hipEventDisableTiming) != hipSuccess) {
@@ -763,10 +764,9 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
         CHK(ws(op, WS_TCOL, (size_t)w * ng + w, &tcol));
         col_w = tcol + (size_t)w * ng;
     }
-    std::vector<int> h_done(w), h_k(w), h_si;
+    std::vector<int> h_done(w), h_k(w), h_kprev(w, 0), h_si;
     std::vector<double> h_t, h_res;
     std::vector<double> h_colw(w, 0.0);
-    int64_t col_iters = 0;
     int launches = 0;
     ChunkGraph cg;
     const bool use_graph = graphs_enabled();
@@ -780,6 +780,14 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
         const int w_geom = std::max(1, running);
         const int nblk_f = fused_partials(op, w_geom);
         int* kstart = kstart_buf[(launches / ch) & 1];
+        // timing: every period-th chunk runs eagerly with its stencil launches
+        // bracketed by events, the others replay as graphs; the GEMM that would
+        // overlap a timed chunk stays on the main stream, so that every timed
+        // launch has the device to itself
+        const int chunk_index = launches / ch;
+        tm->active = tm->on && chunk_index % tm->period == 0;
+        const bool next_timed = tm->on && (chunk_index + 1) % tm->period == 0;
+        hipStream_t gemm_stream = next_timed ? s : side;
         HIPCHK(hipMemcpyAsync(kstart, st.k, w * sizeof(int), hipMemcpyDeviceToDevice, s));
         auto issue = [&]() -> negf_status {
             for (int it = 0; it < steps; ++it) {
@@ -813,10 +821,10 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
         if (gemm_pending) HIPCHK(hipStreamWaitEvent(s, ev_gemm, 0));
         launch_chunk_coef(st, kstart, clen, cx, cp, xi_a, carry, active, s);
         HIPCHK(hipEventRecord(ev_coef, s));
-        HIPCHK(hipStreamWaitEvent(side, ev_coef, 0));
+        HIPCHK(hipStreamWaitEvent(gemm_stream, ev_coef, 0));
         launch_gemm_xp(ring, ring_len, w, n_rows, kstart, clen, st, cx, cp, xi_a, active, X, P,
-                       side);
-        HIPCHK(hipEventRecord(ev_gemm, side));
+                       gemm_stream);
+        HIPCHK(hipEventRecord(ev_gemm, gemm_stream));
         gemm_pending = true;
         HIPCHK(hipGetLastError());
         launches += steps;
@@ -824,6 +832,14 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
         HIPCHK(hipMemcpyAsync(h_k.data(), st.k, w * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         CHK(tm->flush());
+        if (tm->active) {
+            // algorithmic bytes of the timed launches: per column-iteration r and
+            // p_{k-1} in, p_k and q out; V once per launch
+            int64_t ci = 0;
+            for (int c = 0; c < w; ++c) ci += h_k[c] - h_kprev[c];
+            tm->bytes += 4.0 * sizeof(double2) * (double)N * (double)ci + 8.0 * N * steps;
+        }
+        h_kprev = h_k;
         const bool stop = (n_src == w) && launches >= d.max_iter;
         // slots whose column is done hand over its results
         int n_fin = 0;
@@ -855,7 +871,6 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
             for (int c = 0; c < w; ++c) {
                 if (!h_mask[c]) continue;
                 const int j = slot_src[c];
-                col_iters += h_k[c];
                 *total_iters += h_k[c];
                 if (out.h_iters) out.h_iters[j] = h_k[c];
                 if (out.h_status) out.h_status[j] = h_done[c] ? h_done[c] - 1 : NEGF_ITEM_MAX_ITER;
@@ -886,6 +901,8 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
             HIPCHK(hipMemcpyAsync(d_notmask, h_notmask.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
             HIPCHK(hipMemcpyAsync(d_cols, h_colsel.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
             launch_init_unit<double>(r, nullptr, N, w, d_cols, s, d_mask);
+            for (int c = 0; c < w; ++c)
+                if (h_mask[c]) h_kprev[c] = 0;
             for (int c = 0; c < w; ++c) {
                 if (!h_mask[c]) continue;
                 const size_t xo = (size_t)c * ng * n_rows;
@@ -907,10 +924,7 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
         }
         if (!busy) break;
     }
-    if (tm->on) {
-        // per column-iteration: r, p_{k-1} read, p_k, q written; V once per launch
-        tm->bytes += 4.0 * sizeof(double2) * (double)N * (double)col_iters + 8.0 * N * launches;
-    }
+
     if (gemm_pending) HIPCHK(hipStreamWaitEvent(s, ev_gemm, 0));
     if (out.d_out) {
         // column mode: every slot is still live here (n_src == w)
@@ -918,11 +932,6 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
             *total_iters += h_k[c];
             if (out.h_iters) out.h_iters[c] = h_k[c];
             if (out.h_status) out.h_status[c] = h_done[c] ? h_done[c] - 1 : NEGF_ITEM_MAX_ITER;
-        }
-        if (tm->on) {
-            int64_t ci = 0;
-            for (int c = 0; c < w; ++c) ci += h_k[c];
-            tm->bytes += 4.0 * sizeof(double2) * (double)N * (double)ci;
         }
         launch_copy_out(X, n_rows, w, ng, out.d_out, out.out_col_stride, out.out_shift_stride, s);
         if (out.h_resid)
@@ -1195,7 +1204,7 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
     hipStream_t s = pick_stream(op, opts);
     const auto t0 = std::chrono::steady_clock::now();
     MatvecTimer tm;
-    CHK(tm.init(diag && diag->time_matvec));
+    CHK(tm.init(diag ? diag->time_matvec : 0));
     Sides sd;
     make_sides(op, d.direction, &sd);
     CHK(restrict_sides(d, &sd));

@@ -62,3 +62,21 @@ def test_stencil_throughput_floor(gpu_lib):
     gbs = d.extra["matvec_bytes"] / d.extra["matvec_seconds"] / 1e9
     assert d.extra["matvec_launches"] == 256
     assert gbs > 2400.0, gbs
+
+
+def test_sampled_stencil_timing(gpu_lib):
+    """time_matvec = 4 times the launches of every 4th chunk of 128 iterations
+    (chunks 0 and 4 of 8 here) and counts their algorithmic bytes exactly; T is
+    the same as untimed."""
+    import paper_1401_0782_amd as P
+
+    w = make_wire(2)
+    op = P.operator_from_wire(w)
+    P.negf_set_launch_shape(op, 64, 256, 1)
+    kw = dict(n_cols=64, check=False, col_begin=0, col_count=64, block_width=64, max_iter=1024)
+    T4, d4 = P.negf_transmission(op, w.energies, time_matvec=4, **kw)
+    T0, d0 = P.negf_transmission(op, w.energies, **kw)
+    assert d4.extra["matvec_launches"] == 256
+    N = w.N
+    assert d4.extra["matvec_bytes"] == pytest.approx(2 * (4 * 16 * N * 64 * 128 + 8 * N * 128))
+    assert np.array_equal(T4, T0)
