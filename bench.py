@@ -30,7 +30,7 @@ sys.path.insert(0, str(ROOT))
 METRIC = "G-column×energy solves/s at |ΔT|≤1e-6 (mixed vs FP64); matvec HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 TOL = 1e-10
-# the stencil launches of every TIME_EVERY-th chunk of 128 iterations are timed
+# the stencil launches of every TIME_EVERY-th chunk of 256 iterations are timed
 # with HIP events (run eagerly); the other chunks replay as graphs
 TIME_EVERY = 8
 COUNTERS = ROOT / "profiles" / "stencil_wire32x32x192_counters.txt"
@@ -278,7 +278,7 @@ def main():
         "traffic": traffic,  # HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)
         "kernel": kernel + " (fused p = r + beta p, stencil + potential + CAP apply, p^T q partials)",
         "launches": mv_n,
-        "timed_sample": f"stencil launches of every {TIME_EVERY}th chunk of 128 iterations, "
+        "timed_sample": f"stencil launches of every {TIME_EVERY}th chunk of 256 iterations, "
                         f"{mv_n} launches over the timed steps",
         "avg_launch_us": 1e6 * mv_s / max(1, mv_n),
         "bytes_per_launch": mv_b / max(1, mv_n),

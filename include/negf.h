@@ -132,7 +132,7 @@ typedef struct {
     int32_t time_matvec;     /* in: 0 off; 1 brackets every fused stencil launch with
                                 HIP events on the work stream (launched eagerly);
                                 n > 1: in the multi-shift core, the launches of
-                                every n-th chunk of 128 iterations are timed that
+                                every n-th chunk of 256 iterations are timed that
                                 way and the other chunks replay as graphs (the
                                 per-energy core times every launch) */
     double matvec_seconds;   /* out: summed duration of the timed launches */

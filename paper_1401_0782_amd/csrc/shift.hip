@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kT) void k_gemm_xp(const double2* __restrict__ ring
 // 16 x 16 blocks for X and two for P (eight accumulators). The launch bound
 // asks for four waves per SIMD (110 VGPRs, no spills): four work-groups per
 // CU hide the staging loads better than three (10.7 ms against 12.4 ms per
-// 128-iteration chunk on the 32x32x192 wire).
+// chunk of 128 iterations on the 32x32x192 wire).
 typedef double d4_t __attribute__((ext_vector_type(4)));
 constexpr int MK = 16;   // chunk iterations staged per LDS pass
 constexpr int MTN = 32;  // energies per work-group
