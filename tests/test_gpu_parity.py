@@ -135,6 +135,29 @@ def test_chain_one_point_planes(gpu_lib):
         assert np.max(np.abs(T - T_ref)) <= 1e-8, (core, T, T_ref)
 
 
+def test_multishift_single_energy_single_column_and_duplicates(gpu_lib):
+    """Degenerate shift sets of the multi-shift core: one energy (the seed
+    alone), one source column, and repeated energies (zero relative shift),
+    each against the oracle; repeated energies give identical columns."""
+    import paper_1401_0782_amd as P
+
+    w = make_wire(1)
+    op = _op(w)
+    col = rhs_columns(w)[[5]]
+    rows = left_support(w)
+    for E in (np.array([0.35]), np.array([0.3, 0.45, 0.3, 0.45])):
+        out, st = P.negf_solve_columns(op, E, rhs_idx=col, row_idx=rows, tol=1e-12,
+                                       core=P.NEGF_CORE_MULTISHIFT)
+        assert np.all(st == 0)
+        for e, En in enumerate(E):
+            G = O.green_columns(w, En, col, method="dense")
+            err = np.abs(out[e, 0] - G[rows, 0]).max() / np.abs(G).max()
+            assert err < 1e-9, (En, err)
+    assert np.array_equal(out[0], out[2]) and np.array_equal(out[1], out[3])
+    T = P.negf_transmission(op, np.array([0.4]), tol=1e-12)
+    assert abs(T[0] - O.transmission(w, np.array([0.4]), method="dense")[0]) <= 1e-8
+
+
 def test_invalid_calls_rejected(gpu_lib):
     """Empty energy lists, out-of-range shards and null outputs are errors,
     not launches."""
