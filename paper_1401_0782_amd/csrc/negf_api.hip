@@ -696,14 +696,17 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
     CHK(ws(op, WS_RING, (size_t)ring_len * w * n_rows, &ring));
     CHK(ws(op, WS_XS, (size_t)w * ng * n_rows, &X));
     CHK(ws(op, WS_PS, (size_t)w * ng * n_rows, &P));
-    // coefficients: CX, CP [w][ch][ng]; xi_a [w][ng][2]; carry [w][ng]; active [w][ng]
+    // coefficients: CX, CP [w][ch][ng]; xi_a [w][ng][2]; carry [w][ng];
+    // ints: active [w][ng], act_list [w][ng], act_n [w]
     const size_t n_cxp = (size_t)w * ch * ng;
-    CHK(ws(op, WS_COEF, 2 * n_cxp + 3 * (size_t)w * ng + ((size_t)w * ng + 1) / 2, &coef));
+    CHK(ws(op, WS_COEF, 2 * n_cxp + 3 * (size_t)w * ng + ((size_t)w * ng + w + 1) / 2 + 1, &coef));
     double2* cx = coef;
     double2* cp = coef + n_cxp;
     double2* xi_a = coef + 2 * n_cxp;
     double2* carry = xi_a + 2 * (size_t)w * ng;
     int* active = (int*)(carry + (size_t)w * ng);
+    int* act_list = active + (size_t)w * ng;
+    int* act_n = act_list + (size_t)w * ng;
     // per slot: iteration count at the chunk start (two chunks' worth: the GEMM
     // of one chunk overlaps the next), chunk length, slot masks
     int* slots;
@@ -821,11 +824,11 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
         // coefficients here (after the previous GEMM has read its own), the GEMM
         // on the side stream, overlapping the next chunk
         if (gemm_pending) HIPCHK(hipStreamWaitEvent(s, ev_gemm, 0));
-        launch_chunk_coef(st, kstart, clen, cx, cp, xi_a, carry, active, s);
+        launch_chunk_coef(st, kstart, clen, cx, cp, xi_a, carry, active, act_list, act_n, s);
         HIPCHK(hipEventRecord(ev_coef, s));
         HIPCHK(hipStreamWaitEvent(gemm_stream, ev_coef, 0));
-        launch_gemm_xp(ring, ring_len, w, n_rows, kstart, clen, st, cx, cp, xi_a, active, X, P,
-                       gemm_stream);
+        launch_gemm_xp(ring, ring_len, w, n_rows, kstart, clen, st, cx, cp, xi_a, active, act_list,
+                       act_n, X, P, gemm_stream);
         HIPCHK(hipEventRecord(ev_gemm, gemm_stream));
         gemm_pending = true;
         HIPCHK(hipGetLastError());

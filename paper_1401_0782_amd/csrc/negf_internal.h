@@ -199,13 +199,16 @@ void launch_store_rows(const cplx_t<R>* r, int64_t N, int w, const int* rows, in
 // blocked multi-shift accumulation (shift.hip)
 // kstart[c]: the column's iteration count at the start of the chunk; the
 // coefficient kernel writes each column's chunk length to clen for the GEMM
+// active[c][g]: energy g moved in the chunk; act_list/act_n: those energies of
+// each column in order (the matrix-core GEMM tiles them)
 void launch_chunk_coef(const IterState& st, const int* kstart, int* clen, double2* cx,
-                       double2* cp, double2* xi_a, double2* carry, int* active, hipStream_t s);
+                       double2* cp, double2* xi_a, double2* carry, int* active, int* act_list,
+                       int* act_n, hipStream_t s);
 void launch_gemm_xp(const double2* ring, int ring_len, int w, int n_rows, const int* kstart,
                     const int* clen,
                     const IterState& st, const double2* cx, const double2* cp,
-                    const double2* xi_a, const int* active, double2* X, double2* P,
-                    hipStream_t s);
+                    const double2* xi_a, const int* active, const int* act_list,
+                    const int* act_n, double2* X, double2* P, hipStream_t s);
 void launch_t_from_x(const double2* X, int n_rows, int w, int ng, const double* row_w,
                      const double* col_w, const int* only, double* t, hipStream_t s);
 void launch_copy_out(const double2* X, int n_rows, int w, int ng, double2* out, int64_t col_stride,

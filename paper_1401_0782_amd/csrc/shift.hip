@@ -75,6 +75,40 @@ __global__ __launch_bounds__(kT) void k_chunk_coef(IterState st, const int* __re
     active[o] = act;
 }
 
+// The energies a column still iterates on, in order: list[c][0..n[c]) (one
+// work-group per column; a wave ballot and a prefix over the waves per pass of
+// 256 energies).  The GEMM tiles this list, so energies that have converged
+// cost nothing once their 32-energy tile would otherwise stay live.
+__global__ __launch_bounds__(kT) void k_compact_active(const int* __restrict__ active, int ng,
+                                                       int all, int* __restrict__ list,
+                                                       int* __restrict__ n_out) {
+    __shared__ int wave_n[kT / 64];
+    __shared__ int base_sh;
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    if (threadIdx.x == 0) base_sh = 0;
+    __syncthreads();
+    for (int g0 = 0; g0 < ng; g0 += kT) {
+        const int g = g0 + threadIdx.x;
+        const bool f = g < ng && (all || active[(int64_t)c * ng + g] != 0);
+        const unsigned long long m = __ballot(f);
+        const int before = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) wave_n[wave] = __popcll(m);
+        __syncthreads();
+        int off = base_sh;
+        for (int wv = 0; wv < wave; ++wv) off += wave_n[wv];
+        if (f) list[(int64_t)c * ng + off + before] = g;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = 0;
+            for (int wv = 0; wv < kT / 64; ++wv) t += wave_n[wv];
+            base_sh += t;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) n_out[c] = base_sh;
+}
+
 // X <- X + xi o P + R CX and P <- a o P + R CP for one column per grid z.
 // 64 rows x 64 energies per work-group, 4 x 4 of each accumulator per thread.
 constexpr int TM = 64, TN = 64, TK = 16;
@@ -202,26 +236,25 @@ __global__ __launch_bounds__(kT, 4) void k_gemm_xp_mfma(const double2* __restric
                                                      const double2* __restrict__ cx,
                                                      const double2* __restrict__ cp,
                                                      const double2* __restrict__ xi_a,
-                                                     const int* __restrict__ active,
+                                                     const int* __restrict__ act_list,
+                                                     const int* __restrict__ act_n,
                                                      double2* __restrict__ X,
                                                      double2* __restrict__ P) {
     __shared__ double2 sR[MK][TM];
     __shared__ double2 sX[MK][MTN];
     __shared__ double2 sP[MK][MTN];
-    __shared__ int any_active;
+    __shared__ int sg[MTN];  // the tile's energies (-1 past the list)
     const int c = blockIdx.z;
     const int row0 = blockIdx.x * TM;
-    const int g0 = blockIdx.y * MTN;
+    const int t0 = blockIdx.y * MTN;  // tile of the column's list of live energies
     const int ng = st.ng, ch = st.chunk;
     const int k0 = kstart[c];
     const int cl = clen[c];
-    if (cl == 0) return;
+    const int na = act_n[c];
+    if (cl == 0 || t0 >= na) return;
     const int tid = threadIdx.x;
-    if (tid == 0) any_active = 0;
+    if (tid < MTN) sg[tid] = (t0 + tid < na) ? act_list[(int64_t)c * ng + t0 + tid] : -1;
     __syncthreads();
-    if (tid < MTN && g0 + tid < ng && active[(int64_t)c * ng + g0 + tid]) any_active = 1;
-    __syncthreads();
-    if (!any_active) return;
     const int lane = tid % 64, wave = tid / 64;
     const int wr = (wave & 1) * 32, wc = (wave >> 1) * 16;  // the wave's rows / energies
     const int lr = lane % 16, lk = lane / 16;
@@ -243,9 +276,9 @@ __global__ __launch_bounds__(kT, 4) void k_gemm_xp_mfma(const double2* __restric
         }
         for (int e = tid; e < MK * MTN; e += kT) {
             const int jj = e / MTN, gg = e % MTN;
-            const int j = j0 + jj, g = g0 + gg;
+            const int j = j0 + jj, g = sg[gg];
             double2 vx = mk(0.0, 0.0), vp = mk(0.0, 0.0);
-            if (j < cl && g < ng) {
+            if (j < cl && g >= 0) {
                 vx = CX[(int64_t)j * ng + g];
                 vp = CP[(int64_t)j * ng + g];
             }
@@ -278,8 +311,8 @@ __global__ __launch_bounds__(kT, 4) void k_gemm_xp_mfma(const double2* __restric
         }
         __syncthreads();
     }
-    const int g = g0 + wc + lr;
-    if (g >= ng) return;
+    const int g = sg[wc + lr];
+    if (g < 0) return;
     const int64_t o = (int64_t)c * ng + g;
     const double2 xi = xi_a[2 * o], aa = xi_a[2 * o + 1];
     double2* Xg = X + o * n_rows;
@@ -333,16 +366,23 @@ __global__ __launch_bounds__(kT) void k_copy_out(const double2* __restrict__ X, 
 }  // namespace
 
 void launch_chunk_coef(const IterState& st, const int* kstart, int* clen, double2* cx,
-                       double2* cp, double2* xi_a, double2* carry, int* active, hipStream_t s) {
+                       double2* cp, double2* xi_a, double2* carry, int* active, int* act_list,
+                       int* act_n, hipStream_t s) {
     dim3 g((st.ng + kT - 1) / kT, st.w);
     hipLaunchKernelGGL(k_chunk_coef, g, dim3(kT), 0, s, st, kstart, clen, cx, cp, xi_a, carry,
                        active);
+    // NEGF_GEMM_NO_COMPACT=1 lists every energy (a reference for tests: the
+    // frozen ones then get zero coefficients, so X comes out bit for bit the same)
+    const char* e = getenv("NEGF_GEMM_NO_COMPACT");
+    const int all = (e && e[0] == '1') ? 1 : 0;
+    hipLaunchKernelGGL(k_compact_active, dim3(st.w), dim3(kT), 0, s, active, st.ng, all, act_list,
+                       act_n);
 }
 
 void launch_gemm_xp(const double2* ring, int ring_len, int w, int n_rows, const int* kstart,
                     const int* clen, const IterState& st, const double2* cx, const double2* cp,
-                    const double2* xi_a, const int* active, double2* X, double2* P,
-                    hipStream_t s) {
+                    const double2* xi_a, const int* active, const int* act_list,
+                    const int* act_n, double2* X, double2* P, hipStream_t s) {
     dim3 g((n_rows + TM - 1) / TM, (st.ng + TN - 1) / TN, w);
     // NEGF_GEMM_VALU=1 selects the vector-ALU kernel (read per chunk)
     const char* env = getenv("NEGF_GEMM_VALU");
@@ -352,8 +392,8 @@ void launch_gemm_xp(const double2* ring, int ring_len, int w, int n_rows, const 
                            st, cx, cp, xi_a, active, X, P);
     else
         hipLaunchKernelGGL(k_gemm_xp_mfma, dim3(g.x, (st.ng + MTN - 1) / MTN, w), dim3(kT), 0, s,
-                           ring, ring_len, w, n_rows, kstart, clen, st, cx, cp, xi_a, active, X,
-                           P);
+                           ring, ring_len, w, n_rows, kstart, clen, st, cx, cp, xi_a, act_list,
+                           act_n, X, P);
 }
 
 void launch_t_from_x(const double2* X, int n_rows, int w, int ng, const double* row_w,

@@ -94,3 +94,26 @@ def test_mfma_and_valu_shift_accumulation_agree(gpu_lib):
     T_ref = O.transmission(wire, method="dense")
     assert np.max(np.abs(T_m - T_ref)) <= 1e-8
     assert np.max(np.abs(T_v - T_ref)) <= 1e-8
+
+
+def test_live_energy_compaction_is_bit_identical(gpu_lib):
+    """The matrix-core GEMM tiles only the energies that still move; with
+    every energy listed instead, the frozen ones get zero coefficients and
+    T(E) per column comes out bit for bit the same."""
+    import paper_1401_0782_amd as P
+
+    wire = make_wire(1)
+    op = P.operator_from_wire(wire)
+    old = os.environ.get("NEGF_GEMM_NO_COMPACT")
+    try:
+        os.environ["NEGF_GEMM_NO_COMPACT"] = "0"
+        T_c, d_c = P.negf_transmission(op, wire.energies, n_cols=384, tol=1e-12)
+        os.environ["NEGF_GEMM_NO_COMPACT"] = "1"
+        T_a, d_a = P.negf_transmission(op, wire.energies, n_cols=384, tol=1e-12)
+    finally:
+        if old is None:
+            del os.environ["NEGF_GEMM_NO_COMPACT"]
+        else:
+            os.environ["NEGF_GEMM_NO_COMPACT"] = old
+    assert np.array_equal(d_c.t_col, d_a.t_col)
+    assert np.array_equal(d_c.iters, d_a.iters)
