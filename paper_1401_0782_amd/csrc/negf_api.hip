@@ -1962,20 +1962,51 @@ extern "C" negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* op
     std::atomic<int> next{0};
     int device = 0;
     HIPCHK(hipGetDevice(&device));
-    auto worker = [&]() {
+    // Each worker hands one set of workspace buffers from junction to junction.
+    // Junctions run largest first, so later ones usually fit what an earlier one
+    // left: no device allocation or free in between, either of which would
+    // synchronise the device under the other workers' streams.
+    std::vector<std::vector<Buffer>> pools(n_workers, std::vector<Buffer>(WS_COUNT));
+    std::vector<std::vector<void*>> to_free(n_workers);
+    auto worker = [&](int k) {
         (void)hipSetDevice(device);
+        std::vector<Buffer>& pool = pools[k];
         while (true) {
             const int t = next.fetch_add(1);
             if (t >= n_ops) break;
             const int i = order[t];
-            st[i] = transmission_impl(ops[i], opts, n_e[i], energies[i], T[i], nullptr);
+            negf_op* op = ops[i];
+            for (int sl = 0; sl < WS_COUNT; ++sl)
+                if (!op->bufs[sl].ptr) std::swap(op->bufs[sl], pool[sl]);
+            st[i] = transmission_impl(op, opts, n_e[i], energies[i], T[i], nullptr);
             if (st[i] != NEGF_OK) msg[i] = g_last_error;
-            release_workspace(ops[i]);
+            (void)hipStreamSynchronize(op->own_stream);
+            (void)hipStreamSynchronize(op->side_stream);
+            // take the junction's buffers back (the larger one where both exist;
+            // the other is freed after the batch)
+            for (int sl = 0; sl < WS_COUNT; ++sl) {
+                Buffer& b = op->bufs[sl];
+                if (!b.ptr) continue;
+                if (pool[sl].ptr && pool[sl].bytes >= b.bytes) {
+                    to_free[k].push_back(b.ptr);
+                } else {
+                    if (pool[sl].ptr) to_free[k].push_back(pool[sl].ptr);
+                    pool[sl] = b;
+                }
+                b = Buffer{};
+            }
+            op->d_sink = nullptr;
         }
     };
-    std::vector<std::thread> pool;
-    for (int k = 0; k < n_workers; ++k) pool.emplace_back(worker);
-    for (auto& th : pool) th.join();
+    std::vector<std::thread> threads;
+    for (int k = 0; k < n_workers; ++k) threads.emplace_back(worker, k);
+    for (auto& th : threads) th.join();
+    (void)hipDeviceSynchronize();
+    for (auto& v : to_free)
+        for (void* ptr : v) (void)hipFree(ptr);
+    for (auto& pool : pools)
+        for (auto& b : pool)
+            if (b.ptr) (void)hipFree(b.ptr);
     negf_status first = NEGF_OK;
     for (int i = 0; i < n_ops; ++i) {
         if (status) status[i] = st[i];
