@@ -158,6 +158,39 @@ def test_multishift_single_energy_single_column_and_duplicates(gpu_lib):
     assert abs(T[0] - O.transmission(w, np.array([0.4]), method="dense")[0]) <= 1e-8
 
 
+def test_out_of_memory_is_reported_and_recoverable(gpu_lib):
+    """A failed device allocation (forced by the library's test hook on the
+    k-th allocation of a fresh process) surfaces as NEGF_E_OUT_OF_MEMORY with
+    a message, and the process can build and run an operator afterwards."""
+    import os
+    import subprocess
+    import sys
+
+    code = (
+        "import numpy as np, paper_1401_0782_amd as P\n"
+        "from workloads import make_wire\n"
+        "w = make_wire(1)\n"
+        "try:\n"
+        "    P.operator_from_wire(w)\n"
+        "    print('NO-ERROR')\n"
+        "except P.NegfError as e:\n"
+        "    print('STATUS', e.status, str(e))\n"
+        "op = P.operator_from_wire(w)\n"
+        "T = P.negf_transmission(op, w.energies, tol=1e-12)\n"
+        "print('T-OK', bool(np.all(np.isfinite(T))))\n"
+    )
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, NEGF_TEST_FAIL_ALLOC="2", PYTHONPATH=root)
+    out = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True,
+                         text=True, timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    from paper_1401_0782_amd import _abi
+
+    assert f"STATUS {_abi.NEGF_E_OUT_OF_MEMORY}" in out.stdout, out.stdout
+    assert "test hook" in out.stdout
+    assert "T-OK True" in out.stdout
+
+
 def test_invalid_calls_rejected(gpu_lib):
     """Empty energy lists, out-of-range shards and null outputs are errors,
     not launches."""
