@@ -203,7 +203,29 @@ __global__ __launch_bounds__(kThreads) void k_kb_gather(
     if (skip && skip[c]) return;
     const cplx_t<R>* xc = x + (int64_t)c * N;
     double sx = 0, sy = 0;
-    for (int64_t k = off[p] + lane; k < off[p + 1]; k += 64) {
+    int64_t k = off[p] + lane;
+    const int64_t ke = off[p + 1];
+    // four points per lane per step with all their loads issued together (the
+    // index -> value chains are what the gather waits on); each lane still adds
+    // its points in the same order
+    for (; k + 192 < ke; k += 256) {
+        int ii[4];
+        double bb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ii[u] = idx[k + 64 * u];
+            bb[u] = val[k + 64 * u];
+        }
+        cplx_t<R> xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = xc[ii[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            sx += bb[u] * (double)xv[u].x;
+            sy += bb[u] * (double)xv[u].y;
+        }
+    }
+    for (; k < ke; k += 64) {
         const cplx_t<R> xv = xc[idx[k]];
         const double b = val[k];
         sx += b * (double)xv.x;
