@@ -202,32 +202,69 @@ __global__ __launch_bounds__(kT) void k_r_update(cplx_t<R>* __restrict__ r,
 //   scaled residual polynomial value pih = pi * s_0 / s_k, with
 //   pi_{k+1} = (1 + alpha_k delta) pi_k + (alpha_k beta_{k-1}/alpha_{k-1}) (pi_k - pi_{k-1}),
 //   so that ||r^delta_k|| / ||b|| = 1 / |pih_k|.
+// The column's state that the bookkeeping reads, loaded before the partial
+// sums are reduced so that the loads' latency overlaps the reduction: the
+// scalars (thread 0) and the shift state of each thread's first energy.
+struct MsPre {
+    int k;
+    double2 a, bprev, aprev, rho_old;
+    double sk, skm1, s0;
+    int conv;
+    double d;
+    double2 pk, pkm1;
+};
+
+__device__ inline MsPre ms_prefetch(int c, const IterState& st) {
+    MsPre p;
+    p.k = st.k[c];
+    const int k = p.k;
+    if (threadIdx.x == 0) {
+        const double* sh = st.s_hist + (int64_t)c * (st.max_iter + 1);
+        p.a = st.alpha[c];
+        p.bprev = st.beta[c];
+        p.aprev = (k > 0) ? st.a_hist[(int64_t)c * st.max_iter + k - 1] : make_double2(1.0, 0.0);
+        p.rho_old = st.rho[c];
+        p.sk = sh[k];
+        p.skm1 = (k > 0) ? sh[k - 1] : sh[0];
+        p.s0 = sh[0];
+    }
+    if ((int)threadIdx.x < st.ng) {
+        const int64_t o = (int64_t)c * st.ng + threadIdx.x;
+        p.conv = st.sconv[o];
+        p.d = st.deltas[o];
+        p.pk = st.pih[o];
+        p.pkm1 = st.pih_prev[o];
+    }
+    return p;
+}
+
 // Multi-shift bookkeeping of column c, run by one whole work-group once
-// r^T r and ||r||^2 of the new residual are known (valid in thread 0).
-__device__ void ms_bookkeeping(int c, double rr_x, double rr_y, double nn, IterState& st) {
+// r^T r and ||r||^2 of the new residual are known (valid in thread 0); pre
+// holds the state ms_prefetch loaded.
+__device__ void ms_bookkeeping(int c, double rr_x, double rr_y, double nn, IterState& st,
+                               const MsPre& pre) {
     __shared__ double2 sh_sc[6];
     __shared__ int sh_all;
-    const int k = st.k[c];
+    const int k = pre.k;
     if (threadIdx.x == 0) {
         const double2 rho_new = make_double2(rr_x, rr_y);
         const double snew = sqrt(nn);
-        const double2 a = st.alpha[c];
-        const double2 bprev = st.beta[c];
-        const double2 aprev = (k > 0) ? st.a_hist[(int64_t)c * st.max_iter + k - 1] : make_double2(1.0, 0.0);
-        const double2 beta = cdiv(rho_new, st.rho[c]);
-        const double* sh = st.s_hist + (int64_t)c * (st.max_iter + 1);
+        const double2 a = pre.a;
+        const double2 bprev = pre.bprev;
+        const double2 aprev = pre.aprev;
+        const double2 beta = cdiv(rho_new, pre.rho_old);
         st.s_hist[(int64_t)c * (st.max_iter + 1) + k + 1] = snew;
         st.b_hist[(int64_t)c * st.max_iter + k] = beta;
         // scalars for the shift update
         const double2 ck = (k > 0) ? cdiv(cmul(a, bprev), aprev) : make_double2(0.0, 0.0);
-        const double sk = sh[k];
-        const double skm1 = (k > 0) ? sh[k - 1] : sh[0];
+        const double sk = pre.sk;
+        const double skm1 = pre.skm1;
         sh_sc[0] = a;
         sh_sc[1] = ck;
         sh_sc[2] = make_double2(sk / snew, skm1 / snew);
         sh_sc[3] = make_double2(snew, cfinite(beta) ? 1.0 : 0.0);
         sh_sc[4] = beta;
-        sh_sc[5] = make_double2(sh[0] / sk, 0.0);
+        sh_sc[5] = make_double2(pre.s0 / sk, 0.0);
         st.rho[c] = rho_new;
         st.beta[c] = beta;
         st.rnorm[c] = snew;
@@ -242,17 +279,19 @@ __device__ void ms_bookkeeping(int c, double rr_x, double rr_y, double nn, IterS
     int all = 1;
     for (int g = threadIdx.x; g < st.ng; g += blockDim.x) {
         const int64_t o = (int64_t)c * st.ng + g;
+        const bool first = g == (int)threadIdx.x;  // state prefetched
         // A shift whose residual met tol is frozen: its iterate stays the
         // converged one, and shifts far from the seed would otherwise keep
         // converging geometrically until pih overflows.
-        if (st.sconv[o]) {
+        if (first ? pre.conv : st.sconv[o]) {
             rec[g] = mk(0.0, 0.0);
             rec[st.ng + g] = mk(0.0, 0.0);
             rec[2 * st.ng + g] = mk(1.0, 0.0);
             continue;
         }
-        const double d = st.deltas[o];
-        const double2 pk = st.pih[o], pkm1 = st.pih_prev[o];
+        const double d = first ? pre.d : st.deltas[o];
+        const double2 pk = first ? pre.pk : st.pih[o];
+        const double2 pkm1 = first ? pre.pkm1 : st.pih_prev[o];
         // (1 + a d) pk + ck pk, scaled by s_k/s_{k+1}; minus ck pkm1 s_{k-1}/s_{k+1}
         const double2 t1 = cadd(cmul(mk(1.0 + a.x * d, a.y * d), pk), cmul(ck, pk));
         const double2 t2 = cmul(ck, pkm1);
@@ -293,6 +332,7 @@ __global__ __launch_bounds__(kT) void k_reduce_beta_ms(const double2* __restrict
     __shared__ double lds[3 * kT / 64];
     const int c = blockIdx.x;
     if (st.done[c]) return;
+    const MsPre pre = ms_prefetch(c, st);
     double s[3] = {0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < nblk; b += kT) {
         const double2 v = part_rr[(int64_t)c * nblk + b];
@@ -301,7 +341,7 @@ __global__ __launch_bounds__(kT) void k_reduce_beta_ms(const double2* __restrict
         s[2] += part_nn[(int64_t)c * nblk + b];
     }
     block_sum<3>(s, lds);
-    ms_bookkeeping(c, s[0], s[1], s[2], st);
+    ms_bookkeeping(c, s[0], s[1], s[2], st, pre);
 }
 
 // The residual update of a multi-shift COCG iteration, after the fused
