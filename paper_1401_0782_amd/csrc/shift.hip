@@ -219,11 +219,14 @@ __global__ __launch_bounds__(kT) void k_gemm_xp(const double2* __restrict__ ring
 // real ones: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.  A work-group of four
 // waves owns 64 rows x 32 energies; each wave 32 rows x 16 energies as two
 // 16 x 16 blocks for X and two for P (eight accumulators). The launch bound
-// asks for four waves per SIMD (110 VGPRs, no spills): four work-groups per
-// CU hide the staging loads better than three (10.7 ms against 12.4 ms per
-// chunk of 128 iterations on the 32x32x192 wire).
+// asks for four waves per SIMD: four work-groups per CU hid the staging loads
+// better than three (10.7 ms against 12.4 ms per 128 iterations on the
+// 32x32x192 wire).  Staging 8 iterations per pass leaves room in those 128
+// VGPRs to keep the next pass's loads in flight during the MFMAs (+1.3 % on
+// the whole bench against 16 iterations staged without prefetch); the order
+// of the accumulation is the same either way.
 typedef double d4_t __attribute__((ext_vector_type(4)));
-constexpr int MK = 16;   // chunk iterations staged per LDS pass
+constexpr int MK = 8;    // chunk iterations staged per LDS pass
 constexpr int MTN = 32;  // energies per work-group
 
 __device__ inline d4_t mfma4(double a, double b, d4_t c) {
@@ -243,6 +246,7 @@ __global__ __launch_bounds__(kT, 4) void k_gemm_xp_mfma(const double2* __restric
     __shared__ double2 sR[MK][TM];
     __shared__ double2 sX[MK][MTN];
     __shared__ double2 sP[MK][MTN];
+    static_assert(MK * TM == 2 * kT && MK * MTN == kT, "one pass: two ring and one coefficient element per thread");
     __shared__ int sg[MTN];  // the tile's energies (-1 past the list)
     const int c = blockIdx.z;
     const int row0 = blockIdx.x * TM;
@@ -263,29 +267,37 @@ __global__ __launch_bounds__(kT, 4) void k_gemm_xp_mfma(const double2* __restric
     d4_t apr[2] = {zero4, zero4}, api[2] = {zero4, zero4};
     const double2* CX = cx + (int64_t)c * ch * ng;
     const double2* CP = cp + (int64_t)c * ch * ng;
-    for (int j0 = 0; j0 < cl; j0 += MK) {
-        for (int e = tid; e < MK * TM; e += kT) {
-            const int jj = e / TM, rr = e % TM;
-            const int j = j0 + jj, row = row0 + rr;
+    // the next pass's global loads are in flight (registers) while the matrix
+    // cores work on the staged one
+    double2 ra[2], rx, rp;
+    auto fetch = [&](int j0) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = tid + kT * u;
+            const int j = j0 + e / TM, row = row0 + e % TM;
             double2 v = mk(0.0, 0.0);
             if (j < cl && row < n_rows) {
                 const int slot = (k0 + j) % ring_len;
                 v = ring[((int64_t)slot * w + c) * n_rows + row];
             }
-            sR[jj][rr] = v;
+            ra[u] = v;
         }
-        for (int e = tid; e < MK * MTN; e += kT) {
-            const int jj = e / MTN, gg = e % MTN;
-            const int j = j0 + jj, g = sg[gg];
-            double2 vx = mk(0.0, 0.0), vp = mk(0.0, 0.0);
-            if (j < cl && g >= 0) {
-                vx = CX[(int64_t)j * ng + g];
-                vp = CP[(int64_t)j * ng + g];
-            }
-            sX[jj][gg] = vx;
-            sP[jj][gg] = vp;
+        const int j = j0 + tid / MTN, g = sg[tid % MTN];
+        rx = mk(0.0, 0.0);
+        rp = mk(0.0, 0.0);
+        if (j < cl && g >= 0) {
+            rx = CX[(int64_t)j * ng + g];
+            rp = CP[(int64_t)j * ng + g];
         }
+    };
+    fetch(0);
+    for (int j0 = 0; j0 < cl; j0 += MK) {
+        sR[tid / TM][tid % TM] = ra[0];
+        sR[(tid + kT) / TM][(tid + kT) % TM] = ra[1];
+        sX[tid / MTN][tid % MTN] = rx;
+        sP[tid / MTN][tid % MTN] = rp;
         __syncthreads();
+        if (j0 + MK < cl) fetch(j0 + MK);
 #pragma unroll 2
         for (int kk = 0; kk < MK; kk += 4) {
             const double2 a0 = sR[kk + lk][wr + lr];
