@@ -27,56 +27,89 @@ __device__ inline d4_t mfma4(double a, double b, d4_t c) {
 // K[i][j] = sum_{r < n_rows} conj(U[i][row0 + r]) d[r] U[j][row0 + r]   (i, j < n_r)
 // and, when prev != null, out = prev o K (elementwise) instead of K.
 // U: [n_r][N] (eigenvector i contiguous); sel: eigenvector index per row of K.
-__global__ __launch_bounds__(kT) void k_gram(const double2* __restrict__ U, int64_t N,
+// A work-group owns a 64 x 64 tile of K, each wave 32 x 32 as 2 x 2 blocks of
+// 16 x 16; the rows are staged GRK per LDS pass, with the next pass's loads in
+// flight during the MFMAs.  Each element's sum runs over r in order, four
+// rows per MFMA.
+constexpr int GRT = 64;  // Gram tile (rows and columns) per work-group
+constexpr int GRK = 16;  // rows staged per LDS pass
+
+__global__ __launch_bounds__(kT, 3) void k_gram(const double2* __restrict__ U, int64_t N,
                                              const int* __restrict__ sel, int n_r, int64_t row0,
                                              int n_rows, const double* __restrict__ d,
                                              const double2* __restrict__ prev,
                                              double2* __restrict__ out) {
-    __shared__ double2 sA[GK][GT + 1];
-    __shared__ double2 sB[GK][GT + 1];
-    const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
+    static_assert(GRT * GRK == 4 * kT, "four A and four B elements per thread and pass");
+    __shared__ double2 sA[GRK][GRT + 1];
+    __shared__ double2 sB[GRK][GRT + 1];
+    const int i0 = blockIdx.y * GRT, j0 = blockIdx.x * GRT;
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-    const int wm = (wave & 1) * 16, wn = (wave >> 1) * 16;
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
     const int lr = lane % 16, lk = lane / 16;
-    d4_t cr = {0.0, 0.0, 0.0, 0.0}, ci = cr;
-    for (int r0 = 0; r0 < n_rows; r0 += GK) {
-        // stage: one eigenvector per (tile row, slice), the slice contiguous in memory
-        for (int e = tid; e < GT * GK; e += kT) {
-            const int m = e / GK, k = e % GK;
-            const int r = r0 + k;
-            double2 va = mk(0.0, 0.0), vb = mk(0.0, 0.0);
+    const d4_t z4 = {0.0, 0.0, 0.0, 0.0};
+    d4_t cr[2][2] = {{z4, z4}, {z4, z4}}, ci[2][2] = {{z4, z4}, {z4, z4}};
+    double2 va[4], vb[4];
+    auto fetch = [&](int r0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + kT * u;
+            const int m = e / GRK, r = r0 + e % GRK;
+            va[u] = mk(0.0, 0.0);
+            vb[u] = mk(0.0, 0.0);
             if (r < n_rows) {
                 if (i0 + m < n_r) {
-                    const double2 u = U[(int64_t)sel[i0 + m] * N + row0 + r];
-                    va = mk(u.x * d[r], -u.y * d[r]);  // conj(U) d
+                    const double2 x = U[(int64_t)sel[i0 + m] * N + row0 + r];
+                    va[u] = mk(x.x * d[r], -x.y * d[r]);  // conj(U) d
                 }
-                if (j0 + m < n_r) vb = U[(int64_t)sel[j0 + m] * N + row0 + r];
+                if (j0 + m < n_r) vb[u] = U[(int64_t)sel[j0 + m] * N + row0 + r];
             }
-            sA[k][m] = va;
-            sB[k][m] = vb;
+        }
+    };
+    fetch(0);
+    for (int r0 = 0; r0 < n_rows; r0 += GRK) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + kT * u;
+            sA[e % GRK][e / GRK] = va[u];
+            sB[e % GRK][e / GRK] = vb[u];
         }
         __syncthreads();
-#pragma unroll 2
-        for (int kk = 0; kk < GK; kk += 4) {
-            const double2 a = sA[kk + lk][wm + lr];
-            const double2 b = sB[kk + lk][wn + lr];
-            cr = mfma4(a.x, b.x, cr);
-            cr = mfma4(-a.y, b.y, cr);
-            ci = mfma4(a.x, b.y, ci);
-            ci = mfma4(a.y, b.x, ci);
+        if (r0 + GRK < n_rows) fetch(r0 + GRK);
+#pragma unroll
+        for (int kk = 0; kk < GRK; kk += 4) {
+            double2 a[2], b[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                a[q] = sA[kk + lk][wm + 16 * q + lr];
+                b[q] = sB[kk + lk][wn + 16 * q + lr];
+            }
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) {
+                    cr[bi][bj] = mfma4(a[bi].x, b[bj].x, cr[bi][bj]);
+                    cr[bi][bj] = mfma4(-a[bi].y, b[bj].y, cr[bi][bj]);
+                    ci[bi][bj] = mfma4(a[bi].x, b[bj].y, ci[bi][bj]);
+                    ci[bi][bj] = mfma4(a[bi].y, b[bj].x, ci[bi][bj]);
+                }
         }
         __syncthreads();
     }
-    const int j = j0 + wn + lr;
-    if (j >= n_r) return;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int i = i0 + wm + 4 * t + lk;
-        if (i >= n_r) continue;
-        double2 v = mk(cr[t], ci[t]);
-        const int64_t o = (int64_t)i * n_r + j;
-        if (prev) v = cmul(prev[o], v);
-        out[o] = v;
+    for (int bj = 0; bj < 2; ++bj) {
+        const int j = j0 + wn + 16 * bj + lr;
+        if (j >= n_r) continue;
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int i = i0 + wm + 16 * bi + 4 * t + lk;
+                if (i >= n_r) continue;
+                double2 v = mk(cr[bi][bj][t], ci[bi][bj][t]);
+                const int64_t o = (int64_t)i * n_r + j;
+                if (prev) v = cmul(prev[o], v);
+                out[o] = v;
+            }
     }
 }
 
@@ -157,7 +190,7 @@ __global__ __launch_bounds__(kT) void k_sum_tiles(const double* __restrict__ par
 
 void launch_gram(const double2* U, int64_t N, const int* sel, int n_r, int64_t row0, int n_rows,
                  const double* d, const double2* prev, double2* out, hipStream_t s) {
-    dim3 g((n_r + GT - 1) / GT, (n_r + GT - 1) / GT);
+    dim3 g((n_r + GRT - 1) / GRT, (n_r + GRT - 1) / GRT);
     hipLaunchKernelGGL(k_gram, g, dim3(kT), 0, s, U, N, sel, n_r, row0, n_rows, d, prev, out);
 }
 
