@@ -17,8 +17,6 @@ namespace {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 constexpr int kT = 256;
-constexpr int GT = 32;  // output tile (rows and columns) per work-group
-constexpr int GK = 32;  // contraction slice staged per LDS pass
 
 __device__ inline d4_t mfma4(double a, double b, d4_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -114,65 +112,95 @@ __global__ __launch_bounds__(kT, 3) void k_gram(const double2* __restrict__ U, i
 }
 
 // part[tile][e] = sum_{i in tile} Re( conj(a_i(E_e)) sum_j M[i][j] a_j(E_e) ),
-// a_j(E) = 1 / (E - eps_j); one work-group per (32 rows i, 32 energies).
-__global__ __launch_bounds__(kT) void k_eq13(const double2* __restrict__ M, int n_r,
-                                             const double2* __restrict__ eps,
-                                             const double* __restrict__ energies, int n_e,
-                                             double* __restrict__ part) {
-    __shared__ double2 sM[GK][GT + 1];
-    __shared__ double2 sA[GK][GT + 1];
-    __shared__ double red[4][16];
-    const int i0 = blockIdx.x * GT, e0 = blockIdx.y * GT;
+// a_j(E) = 1 / (E - eps_j); one work-group per (64 rows i, 64 energies), each
+// wave 32 x 32 as 2 x 2 blocks; the next slice of M and of a is prepared while
+// the MFMAs run.  Each Y element's sum runs over j in order, four per MFMA.
+__global__ __launch_bounds__(kT, 3) void k_eq13(const double2* __restrict__ M, int n_r,
+                                                const double2* __restrict__ eps,
+                                                const double* __restrict__ energies, int n_e,
+                                                double* __restrict__ part) {
+    static_assert(GRT * GRK == 4 * kT, "four M and four a elements per thread and pass");
+    __shared__ double2 sM[GRK][GRT + 1];
+    __shared__ double2 sA[GRK][GRT + 1];
+    __shared__ double red[4][2][16];
+    const int i0 = blockIdx.x * GRT, e0 = blockIdx.y * GRT;
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-    const int wm = (wave & 1) * 16, wn = (wave >> 1) * 16;
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
     const int lr = lane % 16, lk = lane / 16;
-    d4_t cr = {0.0, 0.0, 0.0, 0.0}, ci = cr;
-    for (int j0 = 0; j0 < n_r; j0 += GK) {
-        for (int e = tid; e < GT * GK; e += kT) {
-            const int m = e / GK, k = e % GK;
-            const int j = j0 + k;
-            double2 vm = mk(0.0, 0.0), va = mk(0.0, 0.0);
-            if (j < n_r) {
-                if (i0 + m < n_r) vm = M[(int64_t)(i0 + m) * n_r + j];
-                if (e0 + m < n_e) va = cdiv(mk(1.0, 0.0), mk(energies[e0 + m] - eps[j].x, -eps[j].y));
-            }
-            sM[k][m] = vm;
-            sA[k][m] = va;
-        }
-        __syncthreads();
-#pragma unroll 2
-        for (int kk = 0; kk < GK; kk += 4) {
-            const double2 a = sM[kk + lk][wm + lr];
-            const double2 b = sA[kk + lk][wn + lr];
-            cr = mfma4(a.x, b.x, cr);
-            cr = mfma4(-a.y, b.y, cr);
-            ci = mfma4(a.x, b.y, ci);
-            ci = mfma4(a.y, b.x, ci);
-        }
-        __syncthreads();
-    }
-    // this lane: Y[i][e] for i = i0 + wm + 4t + lk (t = 0..3), e = e0 + wn + lr
-    const int e = e0 + wn + lr;
-    double s = 0.0;
-    if (e < n_e) {
+    const d4_t z4 = {0.0, 0.0, 0.0, 0.0};
+    d4_t cr[2][2] = {{z4, z4}, {z4, z4}}, ci[2][2] = {{z4, z4}, {z4, z4}};
+    double2 vm[4], va[4];
+    auto fetch = [&](int j0) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int i = i0 + wm + 4 * t + lk;
-            if (i >= n_r) continue;
-            const double2 ai = cdiv(mk(1.0, 0.0), mk(energies[e] - eps[i].x, -eps[i].y));
-            s += ai.x * cr[t] + ai.y * ci[t];  // Re(conj(a_i) y)
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + kT * u;
+            const int m = e / GRK, j = j0 + e % GRK;
+            vm[u] = mk(0.0, 0.0);
+            va[u] = mk(0.0, 0.0);
+            if (j < n_r) {
+                if (i0 + m < n_r) vm[u] = M[(int64_t)(i0 + m) * n_r + j];
+                if (e0 + m < n_e)
+                    va[u] = cdiv(mk(1.0, 0.0), mk(energies[e0 + m] - eps[j].x, -eps[j].y));
+            }
         }
+    };
+    fetch(0);
+    for (int j0 = 0; j0 < n_r; j0 += GRK) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + kT * u;
+            sM[e % GRK][e / GRK] = vm[u];
+            sA[e % GRK][e / GRK] = va[u];
+        }
+        __syncthreads();
+        if (j0 + GRK < n_r) fetch(j0 + GRK);
+#pragma unroll
+        for (int kk = 0; kk < GRK; kk += 4) {
+            double2 a[2], b[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                a[q] = sM[kk + lk][wm + 16 * q + lr];
+                b[q] = sA[kk + lk][wn + 16 * q + lr];
+            }
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) {
+                    cr[bi][bj] = mfma4(a[bi].x, b[bj].x, cr[bi][bj]);
+                    cr[bi][bj] = mfma4(-a[bi].y, b[bj].y, cr[bi][bj]);
+                    ci[bi][bj] = mfma4(a[bi].x, b[bj].y, ci[bi][bj]);
+                    ci[bi][bj] = mfma4(a[bi].y, b[bj].x, ci[bi][bj]);
+                }
+        }
+        __syncthreads();
     }
-    // the four lanes of one energy (lk = 0..3), then the two waves of one energy column
-    s += __shfl_xor(s, 16, 64);
-    s += __shfl_xor(s, 32, 64);
-    if (lk == 0) red[wave][lr] = s;
+    // this lane: Y[i][e] for i = i0 + wm + 16 bi + 4t + lk, e = e0 + wn + 16 bj + lr
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+        const int e = e0 + wn + 16 * bj + lr;
+        double s = 0.0;
+        if (e < n_e) {
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int i = i0 + wm + 16 * bi + 4 * t + lk;
+                    if (i >= n_r) continue;
+                    const double2 ai = cdiv(mk(1.0, 0.0), mk(energies[e] - eps[i].x, -eps[i].y));
+                    s += ai.x * cr[bi][bj][t] + ai.y * ci[bi][bj][t];  // Re(conj(a_i) y)
+                }
+        }
+        // the four lanes of one energy (lk = 0..3)
+        s += __shfl_xor(s, 16, 64);
+        s += __shfl_xor(s, 32, 64);
+        if (lk == 0) red[wave][bj][lr] = s;
+    }
     __syncthreads();
-    if (tid < GT) {
-        const int wc = tid / 16, l = tid % 16;  // energy column half, lane
-        const int ee = e0 + wc * 16 + l;
-        // waves (0, 1) hold energies e0 .. e0 + 15, waves (2, 3) the next 16
-        if (ee < n_e) part[(int64_t)blockIdx.x * n_e + ee] = red[2 * wc][l] + red[2 * wc + 1][l];
+    if (tid < GRT) {
+        // waves (0, 1) hold energies e0 .. e0 + 31, waves (2, 3) the next 32
+        const int wc = tid / 32, bj = (tid / 16) % 2, l = tid % 16;
+        const int ee = e0 + tid;
+        if (ee < n_e) part[(int64_t)blockIdx.x * n_e + ee] = red[2 * wc][bj][l] + red[2 * wc + 1][bj][l];
     }
 }
 
@@ -194,11 +222,11 @@ void launch_gram(const double2* U, int64_t N, const int* sel, int n_r, int64_t r
     hipLaunchKernelGGL(k_gram, g, dim3(kT), 0, s, U, N, sel, n_r, row0, n_rows, d, prev, out);
 }
 
-int eq13_tiles(int n_r) { return (n_r + GT - 1) / GT; }
+int eq13_tiles(int n_r) { return (n_r + GRT - 1) / GRT; }
 
 void launch_eq13(const double2* M, int n_r, const double2* eps, const double* energies, int n_e,
                  double* part, double* T, hipStream_t s) {
-    dim3 g(eq13_tiles(n_r), (n_e + GT - 1) / GT);
+    dim3 g(eq13_tiles(n_r), (n_e + GRT - 1) / GRT);
     hipLaunchKernelGGL(k_eq13, g, dim3(kT), 0, s, M, n_r, eps, energies, n_e, part);
     hipLaunchKernelGGL(k_sum_tiles, dim3((n_e + kT - 1) / kT), dim3(kT), 0, s, part, eq13_tiles(n_r),
                        n_e, T);
