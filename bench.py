@@ -178,7 +178,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--block", type=int, default=64, help="source columns per step")
-    ap.add_argument("--max-iter", type=int, default=30000)
+    ap.add_argument("--max-iter", type=int, default=60000)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
