@@ -218,13 +218,13 @@ negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* ops, const ne
  * count, and to widths whose workspace at opts->max_iter fits in half of the
  * free device memory; only opts->block_width when that is nonzero) x stencil
  * work-group targets
- * 128, 256, 512, 1024 per launch x {whole-plane kernel, row-tiled kernel}
+ * 128, 192, 256, 512, 1024 per launch x {whole-plane kernel, row-tiled kernel}
  * (the whole-plane kernel only where one plane fits a work-group).
  * Results are identical up to rounding for every candidate: only the launch
  * shape changes.  Probes that hit max_iter are expected and not errors.
  *   opts      direction, shift_group, block_width and stream are read
  *   result    nullable; receives the choice and the timing table */
-#define NEGF_TUNE_MAX 40
+#define NEGF_TUNE_MAX 64
 typedef struct {
     int32_t block_width;  /* chosen source columns per block */
     int32_t wg_target;    /* chosen stencil work-groups per launch (z-chunking) */

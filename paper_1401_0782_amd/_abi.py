@@ -67,7 +67,7 @@ class negf_diag(C.Structure):
                 ("matvec_bytes", C.c_double)]
 
 
-NEGF_TUNE_MAX = 40
+NEGF_TUNE_MAX = 64
 
 
 class negf_tune_result(C.Structure):

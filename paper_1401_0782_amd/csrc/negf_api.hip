@@ -1657,7 +1657,7 @@ static negf_status tune_impl(negf_op* op, const negf_opts* opts, int32_t n_e,
     std::vector<Cand> cands;
     for (int w : widths)
         for (int k : kernels)
-            for (int t : {128, 256, 512, 1024}) cands.push_back({w, t, k, 0.0});
+            for (int t : {128, 192, 256, 512, 1024}) cands.push_back({w, t, k, 0.0});
     if ((int)cands.size() > NEGF_TUNE_MAX) cands.resize(NEGF_TUNE_MAX);
 
     double* d_roww = nullptr;

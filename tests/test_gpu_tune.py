@@ -17,8 +17,8 @@ def test_tune_picks_fastest_candidate_and_keeps_results(gpu_lib):
     T_default = P.negf_transmission(op, wire.energies, tol=1e-12)
     res = P.negf_tune(op, wire.energies)
     tried = res["tried"]
-    # 5 widths x 2 stencil kernels (the 64-point plane fits one work-group) x 4 targets
-    assert len(tried) == 40
+    # 5 widths x 2 stencil kernels (the 64-point plane fits one work-group) x 5 targets
+    assert len(tried) == 50
     assert {t[0] for t in tried} == {16, 32, 64, 128, 256}
     assert {t[2] for t in tried} == {0, 1}
     assert all(t[3] > 0 for t in tried)
