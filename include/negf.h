@@ -207,7 +207,8 @@ negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* ops, const ne
 
 /* Launch-shape autotuner for the multi-shift core (the batching form's
  * tuned block width, z-chunking and stencil kernel).  It times a short run of
- * probe_iters COCG iterations (0 -> 256: one chunk, so one blocked shift
+ * probe_iters COCG iterations (0 -> one chunk: 128 iterations, 256 on grids of
+ * 131,072 points or more; so one blocked shift
  * accumulation is included) of the op's first source columns at the given
  * energies for every candidate, on the op's stream, and keeps the candidate
  * with the least device time per column-iteration in the op.  Later

@@ -645,10 +645,12 @@ struct MSOut {
     int* h_shift_iters = nullptr; // [n_src][ng] iteration at which each energy converged (0: not)
 };
 
-// iterations per blocked shift update (and per ring half)
-// (256 moved 0.9 % more solves/s than 128 on the 32x32x192 wire: X and P are
-// read and written once per chunk; 384 was slower again)
-static constexpr int kShiftChunk = 256;
+// iterations per blocked shift update (and per ring half).  X and P move once
+// per chunk, so long chunks pay on large grids (256 ran 0.9 % faster than 128
+// on the 32x32x192 wire, 384 was slower); streamed slots refill only at chunk
+// boundaries, so small grids, whose columns converge in ~100 iterations, keep
+// 128 (the 8x8x32 wire: 113k solves/s at 256, 122k at 128).
+static int shift_chunk(const negf_op* op) { return op->N >= 131072 ? 256 : 128; }
 
 // The multi-shift core (FP64) on a block of w column slots.
 //   cols (host, n_src entries) unit right-hand sides, or d_rhs (device [w][N])
@@ -674,7 +676,7 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
     const int nblk_f_max = fused_partials(op, 1);
     // ring of 2c + 1 slots: while the GEMM of chunk j reads its c residuals,
     // chunk j + 1 stores the next c + 1 without touching them
-    const int ch = kShiftChunk, ring_len = 2 * kShiftChunk + 1;
+    const int ch = shift_chunk(op), ring_len = 2 * ch + 1;
     if (n_src < w || (n_src > w && (!cols || out.d_out))) {
         set_error("internal: column streaming needs unit right-hand sides in transmission mode");
         return NEGF_E_INVALID_ARG;
@@ -1606,7 +1608,7 @@ static void release_workspace(negf_op* op) {
 // ---------------------------------------------------------------------------
 // device bytes of run_multishift_block's workspace for a block of w columns
 static double multishift_bytes(const negf_op* op, int w, int ng, int n_rows, int max_iter) {
-    const double N = (double)op->N, ch = kShiftChunk, z = sizeof(double2);
+    const double N = (double)op->N, ch = shift_chunk(op), z = sizeof(double2);
     const double vec = 4.0 * w * N * z;                             // r, p (x2), q
     const double ring = 2.0 * ch * w * n_rows * z;
     const double xp = 2.0 * w * (double)ng * n_rows * z;
@@ -1632,7 +1634,7 @@ static negf_status tune_impl(negf_op* op, const negf_opts* opts, int32_t n_e,
     const int n_cols = (int)sd.cols.size();
     const int ng = d.shift_group ? std::min(d.shift_group, n_e) : n_e;
     Defaults dp = d;
-    dp.max_iter = probe_iters ? probe_iters : kShiftChunk;
+    dp.max_iter = probe_iters ? probe_iters : shift_chunk(op);
 
     // widths whose multi-shift workspace (at the caller's max_iter) fits in
     // half of the free device memory
