@@ -18,6 +18,7 @@
 
 #include <mutex>
 #include <set>
+#include <type_traits>
 #include <utility>
 
 #include "negf_internal.h"
@@ -341,6 +342,22 @@ template void launch_apply<float>(const negf_op*, const float2*, float2*, int, c
 // p_k is written by the owner of each plane only (no write races), and the
 // p buffers ping-pong between iterations so halo reads see p_{k-1}.
 // ---------------------------------------------------------------------------
+// p = r + beta p_prev with the roundings fixed (explicit fused multiply-adds),
+// so every thread that forms the same element (its owner, or a neighbouring
+// tile's y-halo) gets the same bits
+template <typename R>
+__device__ __forceinline__ cplx_t<R> cocg_p(const cplx_t<R>& rv, const cplx_t<R>& pv, R bx, R by) {
+    cplx_t<R> o;
+    if constexpr (std::is_same<R, double>::value) {
+        o.x = __builtin_fma(bx, pv.x, __builtin_fma(-by, pv.y, rv.x));
+        o.y = __builtin_fma(bx, pv.y, __builtin_fma(by, pv.x, rv.y));
+    } else {
+        o.x = __builtin_fmaf(bx, pv.x, __builtin_fmaf(-by, pv.y, rv.x));
+        o.y = __builtin_fmaf(bx, pv.y, __builtin_fmaf(by, pv.x, rv.y));
+    }
+    return o;
+}
+
 template <int RAD, typename R, int NT, bool FUSED>
 __global__ __launch_bounds__(NT) void k_cocg_apply(
     const cplx_t<R>* __restrict__ r, const cplx_t<R>* __restrict__ pin, cplx_t<R>* __restrict__ pout,
@@ -368,7 +385,7 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
     const int lx = tid % nx;
     const int ly = tid / nx;  // < rows for the threads that own a point
     const bool own = ly < rows;
-    const int64_t col_off = (int64_t)(y0 + (own ? ly : 0)) * nx + lx;
+    const int col_off = (y0 + (own ? ly : 0)) * nx + lx;  // within a plane
     const double e_c = shift[c] + a0;
     const bool first = FUSED ? (kit[c] == 0) : true;
     const double2 bb = FUSED ? beta[c] : make_double2(0.0, 0.0);
@@ -380,11 +397,7 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
         if (!FUSED) return pin[co + gi];
         const cplx_t<R> rv = r[co + gi];
         if (first) return rv;
-        const cplx_t<R> pv = pin[co + gi];
-        cplx_t<R> o;
-        o.x = rv.x + bx * pv.x - byy * pv.y;
-        o.y = rv.y + bx * pv.y + byy * pv.x;
-        return o;
+        return cocg_p<R>(rv, pin[co + gi], bx, byy);
     };
 
     // zero both LDS tiles (x padding and out-of-grid rows stay zero)
@@ -434,8 +447,7 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
             } else if (first) {
                 lead = nr;
             } else {
-                lead.x = nr.x + bx * np.x - byy * np.y;
-                lead.y = nr.y + bx * np.y + byy * np.x;
+                lead = cocg_p<R>(nr, np, bx, byy);
             }
             q[2 * RAD] = lead;
         }
@@ -754,17 +766,16 @@ void fused_launch(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin, c
                            part);
         return;
     }
-    if (g.lds > 65536)
-        allow_large_lds(g.nt == 256 ? (const void*)k_cocg_apply<RAD, R, 256, FUSED>
-                                    : (const void*)k_cocg_apply<RAD, R, 1024, FUSED>);
+    auto go = [&](auto kern, int nt) {
+        if (g.lds > 65536) allow_large_lds((const void*)kern);
+        hipLaunchKernelGGL(kern, grid, dim3(nt), g.lds, s, r, pin, pout, y, op->nx, op->ny,
+                           op->nz, g.ty, g.n_ytiles, g.zchunk, cf, op->coef.a[0], op->d_v,
+                           op->d_wz, shift, skip, kit, beta, part);
+    };
     if (g.nt == 256)
-        hipLaunchKernelGGL((k_cocg_apply<RAD, R, 256, FUSED>), grid, dim3(256), g.lds, s, r, pin,
-                           pout, y, op->nx, op->ny, op->nz, g.ty, g.n_ytiles, g.zchunk, cf,
-                           op->coef.a[0], op->d_v, op->d_wz, shift, skip, kit, beta, part);
+        go(k_cocg_apply<RAD, R, 256, FUSED>, 256);
     else
-        hipLaunchKernelGGL((k_cocg_apply<RAD, R, 1024, FUSED>), grid, dim3(1024), g.lds, s, r, pin,
-                           pout, y, op->nx, op->ny, op->nz, g.ty, g.n_ytiles, g.zchunk, cf,
-                           op->coef.a[0], op->d_v, op->d_wz, shift, skip, kit, beta, part);
+        go(k_cocg_apply<RAD, R, 1024, FUSED>, 1024);
 }
 
 }  // namespace

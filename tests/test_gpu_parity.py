@@ -122,6 +122,28 @@ def test_solve_columns_match_oracle(gpu_lib):
             assert err < 1e-9, (core, e, err)
 
 
+def test_row_tiled_planes_with_y_halo(gpu_lib):
+    """Planes of 8 x 132 points (above the whole-plane kernel's 1024) split
+    into two y-tiles of the row-tiled stencil kernel, each reading R rows of
+    its neighbour: columns of G on both sides of the tile boundary against
+    the oracle."""
+    import paper_1401_0782_amd as P
+
+    nx, ny, nz, h = 8, 132, 24, 0.5
+    w = make_custom(nx, ny, nz, h, 2, 5, np.linspace(0.4, 1.0, 2),
+                    wells=[((nx + 1) * h / 2, (ny + 1) * h / 2, (nz + 1) * h / 2, 0.6)])
+    op = _op(w)
+    # row 128 starts the second tile of 1024 / nx rows
+    cols = rhs_columns(w)[[0, 127 * nx + 3, 128 * nx + 5, 777]]
+    rows = np.concatenate([left_support(w)[::29], np.arange(w.N - 3 * nx * ny, w.N, 41)])
+    out, st = P.negf_solve_columns(op, w.energies, rhs_idx=cols, row_idx=rows, tol=1e-12)
+    assert np.all(st == 0)
+    for e, E in enumerate(w.energies):
+        Gfull = O.green_columns(w, E, cols)
+        err = (np.abs(out[e].T - Gfull[rows]) / np.abs(Gfull).max(axis=0)).max()
+        assert err < 1e-9, (e, err)
+
+
 def test_chain_one_point_planes(gpu_lib):
     """The degenerate 1 x 1 x nz grid (a chain; planes of one point, the
     row-tiled stencil kernel) with long CAPs: both cores against the oracle."""
