@@ -171,6 +171,124 @@ def cpu_baseline(seconds: float):
     }
 
 
+# ---------------------------------------------------------- secondary rows
+FP64_PEAK_TFS = 78.6
+ROWS = ("small", "batch", "full", "adjoint", "large", "spectral", "current")
+
+
+def measure_rows(names):
+    """Secondary measurements (one JSON line each): the other workloads and
+    forms of the path, timed whole on the host clock around synchronised
+    calls, each after a warm-up call (the same call, or one on fewer columns;
+    none for the 64x64x256 wire).  Not the headline line."""
+    import numpy as np
+    import torch
+
+    import paper_1401_0782_amd as P
+    from workloads import make_custom, make_junctions, make_wire, rhs_columns
+
+    def emit(**kw):
+        print(json.dumps(kw), flush=True)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t
+
+    for name in names:
+        if name == "small":
+            w = make_wire(1)
+            op = P.operator_from_wire(w)
+            n, E = len(rhs_columns(w)), w.energies
+            P.negf_transmission(op, E, tol=TOL)
+            ref, t = timed(lambda: P.negf_transmission(op, E, tol=TOL))
+            emit(row=name, workload=f"wire 8x8x32 R=2, {n} cols x {E.size} E", form="core B FP64",
+                 seconds=t, solves_per_s=n * E.size / t)
+            for form, kw in [("core A FP64 COCG", dict(core=P.NEGF_CORE_PER_ENERGY)),
+                             ("core A FP64 QMR", dict(core=P.NEGF_CORE_PER_ENERGY,
+                                                      solver=P.NEGF_SOLVER_QMR)),
+                             ("core A mixed COCG", dict(precision=P.NEGF_MIXED)),
+                             ("core A mixed QMR", dict(precision=P.NEGF_MIXED,
+                                                       solver=P.NEGF_SOLVER_QMR))]:
+                P.negf_transmission(op, E, tol=TOL, **kw)
+                T, t = timed(lambda: P.negf_transmission(op, E, tol=TOL, **kw))
+                emit(row=name, form=form, seconds=t, solves_per_s=n * E.size / t,
+                     max_dT_vs_core_B=float(np.abs(T - ref).max()))
+        elif name == "batch":
+            js = make_junctions(64)
+            ops = [P.operator_from_wire(j) for j in js]
+            es = [j.energies for j in js]
+            cols = 16
+            run = lambda k: P.negf_transmission_batch(ops, es, tol=TOL, col_begin=0, col_count=k)
+            run(1)
+            (_, st), t = timed(lambda: run(cols))
+            solves = sum(cols * e.size for e in es)
+            emit(row=name, workload=f"64 junctions 16^2x64..40^2x160, {cols} cols x all E",
+                 form="batch, core B FP64", seconds=t, solves=solves, solves_per_s=solves / t,
+                 statuses_ok=bool(np.all(st == 0)))
+        elif name in ("full", "adjoint"):
+            w = make_wire(4)
+            op = P.operator_from_wire(w)
+            E, n = w.energies, len(rhs_columns(w))
+            if name == "full":
+                P.negf_transmission(op, E, tol=TOL, col_begin=0, col_count=64)
+                _, t = timed(lambda: P.negf_transmission(op, E, tol=TOL))
+                emit(row=name, workload=f"wire 24x24x96 R=4, all {n} cols x {E.size} E",
+                     form="core B FP64", seconds=t, solves_per_s=n * E.size / t)
+            else:
+                wts = np.ones(E.size)
+                run = lambda k: P.negf_transmission_grad(op, E, wts, tol=TOL, col_begin=0,
+                                                         col_count=k)
+                run(2)
+                _, t = timed(lambda: run(32))
+                emit(row=name, workload=f"wire 24x24x96 R=4, 32 cols x {E.size} E",
+                     form="dT/dV: core A forward + adjoint solves", seconds=t,
+                     item_solves_per_s=2 * 32 * E.size / t)
+        elif name == "large":
+            w = make_wire(5)
+            op = P.operator_from_wire(w)
+            E, cols = w.energies, 16
+            run = lambda: P.negf_transmission(op, E, n_cols=cols, check=False, tol=TOL,
+                                              col_begin=0, col_count=cols, block_width=cols)
+            (_, d), t = timed(run)  # one 16-column block of ~50 s: not repeated
+            emit(row=name, workload=f"wire 64x64x256 R=6 KB, {cols} cols x {E.size} E",
+                 form="core B FP64 (cold)", seconds=t, solves_per_s=cols * E.size / t,
+                 status=int(d.status))
+        elif name == "spectral":
+            # the work depends only on the shapes: random eigenpairs of that size
+            w = make_custom(16, 16, 80, 0.5, 4, 10, np.linspace(0.1, 1.0, 1024))
+            op = P.operator_from_wire(w)
+            n_r, n_l = 2048, 16 * 16 * 10
+            rng = np.random.default_rng(5)
+            eps = rng.uniform(0, 1.2, n_r) - 1j * rng.uniform(1e-3, 0.1, n_r)
+            g = torch.Generator(device="cuda").manual_seed(5)
+            U = torch.randn(n_r, w.N, dtype=torch.complex128, device="cuda", generator=g)
+            run = lambda: P.negf_spectral_transmission(op, eps, U, w.energies)
+            run()
+            reps = 5
+            _, t = timed(lambda: [run() for _ in range(reps)])
+            # two Gram products (left, right CAP rows) and Eq. 13, complex FP64
+            flops = 2 * 8.0 * n_r * n_r * n_l + 8.0 * n_r * n_r * w.energies.size
+            emit(row=name, workload=f"{n_r} eigenpairs, {n_l} CAP rows per side, "
+                 f"{w.energies.size} E", form="Eqs. 8-13 on FP64 MFMA",
+                 ms_per_call=1e3 * t / reps, gflop_per_call=flops / 1e9,
+                 tflops=flops * reps / t / 1e12,
+                 frac_fp64_peak=flops * reps / t / 1e12 / FP64_PEAK_TFS)
+        elif name == "current":
+            n_e, n_b = 1 << 20, 64
+            E = np.linspace(-1.0, 1.0, n_e)
+            T = 1.0 / (1.0 + np.exp(-8 * E))
+            bias = np.linspace(0.01, 0.5, n_b)
+            P.negf_current(E, T, bias, 0.0, 0.01)
+            _, t = timed(lambda: P.negf_current(E, T, bias, 0.0, 0.01))
+            emit(row=name, workload=f"{n_e} energies x {n_b} biases",
+                 form="Eq. 1, host arrays in and out", ms_per_call=1e3 * t)
+        else:
+            raise SystemExit(f"unknown row {name!r}: choose from {', '.join(ROWS)}")
+
+
 # ---------------------------------------------------------------- GPU leg
 def main():
     ap = argparse.ArgumentParser()
@@ -188,6 +306,9 @@ def main():
     ap.add_argument("--oracle-iterations", type=str, default=None, metavar="E_IDX,...",
                     help="CPU only: run the oracle's BiCGSTAB to completion at these energy "
                          "indices and print the iteration counts (the CPU baseline's scale)")
+    ap.add_argument("--rows", type=str, default=None, metavar="ROW,...",
+                    help="instead of the headline step, time other workloads and forms: "
+                         + ", ".join(ROWS))
     args = ap.parse_args()
     if args.oracle_iterations:
         measure_oracle_iterations([int(v) for v in args.oracle_iterations.split(",")])
@@ -204,6 +325,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.rows:
+        measure_rows(args.rows.split(","))
+        return
     import paper_1401_0782_amd as P
     from workloads import make_wire, rhs_columns
 
