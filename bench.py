@@ -351,7 +351,7 @@ def main():
         tuned = {"block_width": args.block, "wg_target": tgt, "plane_kernel": plane}
     else:
         tuned = P.negf_tune(op, wire.energies, block_width=args.block)
-    plane_fits = wire.nx * wire.ny <= 1024 and (wire.nx * wire.ny) % 64 == 0
+    plane_fits = wire.nx * wire.ny <= 1024
     kernel = KERNELS[1 if (tuned["plane_kernel"] != 0 and plane_fits) else 0]
     print(f"tuned launch shape: block {tuned['block_width']}, stencil work-groups "
           f"{tuned['wg_target']}, whole-plane kernel {tuned['plane_kernel']}",

@@ -1653,7 +1653,7 @@ static negf_status tune_impl(negf_op* op, const negf_opts* opts, int32_t n_e,
         if (widths.empty()) widths.push_back(std::min(16, n_cols));
     }
     const int pts = op->nx * op->ny;
-    const bool plane_ok = pts <= 1024 && pts % 64 == 0;
+    const bool plane_ok = pts <= 1024;
     std::vector<int> kernels = plane_ok ? std::vector<int>{1, 0} : std::vector<int>{0};
     struct Cand { int w, target, plane; double us; };
     std::vector<Cand> cands;

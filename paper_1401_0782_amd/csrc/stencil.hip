@@ -538,9 +538,10 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
     }
 }
 
-// Whole-plane variant of k_cocg_apply: the work-group is exactly one z-plane
-// of one column (blockDim = nx*ny <= 1024, a multiple of the wave size), so
-// there is no y-halo and every thread owns a point.  Two things keep the
+// Whole-plane variant of k_cocg_apply: the work-group is one z-plane of one
+// column (blockDim = nx*ny <= 1024 rounded up to whole waves), so there is no
+// y-halo and every thread owns a point (the padding lanes mirror the last
+// one and store nothing that is kept).  Two things keep the
 // in-order vector-memory queue from draining every plane:
 //  * all global loads and stores are unconditional (plane indices clamped,
 //    out-of-grid values discarded by selection, stores that belong to no plane
@@ -568,8 +569,14 @@ __global__ __launch_bounds__(1024) void k_cocg_plane(
     const int64_t plane = (int64_t)nx * ny;
     const int64_t co = (int64_t)c * plane * nz;
     const int tid = threadIdx.x;
-    const int lx = tid % nx, ly = tid / nx;
-    const int64_t col_off = tid;  // = ly * nx + lx
+    // lanes past the plane (the block is padded to whole waves) mirror its
+    // last point: same loads, same LDS value at the same place, every global
+    // store sunk and no share in the dot product
+    const int pts = nx * ny;
+    const bool ghost = tid >= pts;
+    const int pt = ghost ? pts - 1 : tid;
+    const int lx = pt % nx, ly = pt / nx;
+    const int64_t col_off = pt;  // = ly * nx + lx
     const int lds_at = (ly + RAD) * pitch + RAD + lx;
     cplx_t<R>* my_sink = sink + (int64_t)c * plane + col_off;
     const double e_c = shift[c] + a0;
@@ -634,7 +641,7 @@ __global__ __launch_bounds__(1024) void k_cocg_plane(
             v_next = v[(int64_t)min(z + 1, nz - 1) * plane + col_off];
             const cplx_t<R> xi = q[(u + RAD) % Q];
             tile[lds_at] = xi;
-            const bool live = z < z1;
+            const bool live = z < z1 && !ghost;
             const int64_t gz = co + (int64_t)min(z, nz - 1) * plane + col_off;
             if (FUSED) {
                 cplx_t<R>* dst = live ? pout + gz : my_sink;
@@ -705,10 +712,10 @@ FusedGeom fused_geom(const negf_op* op, int w) {
     FusedGeom g;
     const int nx = op->nx, ny = op->ny, nz = op->nz;
     const int pts = nx * ny;
-    g.whole_plane = pts <= 1024 && pts % 64 == 0 && op->plane_kernel != 0 &&
+    g.whole_plane = pts <= 1024 && op->plane_kernel != 0 &&
                     getenv("NEGF_NO_PLANE_KERNEL") == nullptr;
     if (g.whole_plane) {
-        g.nt = pts;
+        g.nt = (pts + 63) / 64 * 64;
         g.ty = ny;
         g.n_ytiles = 1;
         // z-chunks: enough work-groups for every CU, each a multiple of the
