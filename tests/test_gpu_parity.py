@@ -145,13 +145,18 @@ def test_row_tiled_planes_with_y_halo(gpu_lib):
 
 
 def test_chain_one_point_planes(gpu_lib):
-    """The degenerate 1 x 1 x nz grid (a chain; planes of one point, the
-    row-tiled stencil kernel) with long CAPs: both cores against the oracle."""
+    """The degenerate 1 x 1 x nz grid (a chain; planes of one point, so the
+    whole-plane kernel's block is one point and 63 padding lanes) with long
+    CAPs: both cores against the oracle.  The band of this chain starts at
+    10 Ha (the two transverse second differences of the one-point planes add
+    5 Ha each at h = 0.5, R = 2), so the energies sit inside it, where the
+    long CAPs give T close to 1."""
     import paper_1401_0782_amd as P
 
-    w = make_custom(1, 1, 200, 0.5, 2, 80, np.linspace(0.3, 3.0, 6), w0=0.5)
+    w = make_custom(1, 1, 120, 0.5, 2, 40, np.linspace(10.3, 13.0, 6), w0=0.5)
     op = _op(w)
     T_ref = O.transmission(w, method="dense")
+    assert T_ref.min() > 0.9
     for core in (P.NEGF_CORE_MULTISHIFT, P.NEGF_CORE_PER_ENERGY):
         T = P.negf_transmission(op, w.energies, tol=1e-12, core=core)
         assert np.max(np.abs(T - T_ref)) <= 1e-8, (core, T, T_ref)

@@ -21,7 +21,9 @@ def _eigenpairs(wire):
 
 @pytest.fixture(scope="module")
 def kb_wire():
-    return make_custom(5, 4, 24, 0.5, 3, 4, np.linspace(0.3, 0.9, 9),
+    # energies across the first transverse thresholds (~1.3 Ha for this
+    # cross-section): T from 1e-10 to ~0.95
+    return make_custom(5, 4, 24, 0.5, 3, 4, np.linspace(1.0, 2.6, 9),
                        wells=[(1.4, 1.1, 5.0, 0.5), (1.7, 1.3, 7.5, 0.3)],
                        atoms_kb=[(0.8, 0.3, 0.1), (0.7, 0.2, 0.12)])
 
@@ -35,6 +37,7 @@ def test_spectral_route_all_eigenpairs(gpu_lib, kb_wire):
     T = P.negf_spectral_transmission(op, eps, U, E)
     T_sp = O.transmission_spectral(kb_wire, E)
     T_ls = O.transmission(kb_wire, E, method="dense")
+    assert T_ls.max() > 0.5
     np.testing.assert_allclose(T, T_sp, rtol=1e-9, atol=1e-12)
     assert np.max(np.abs(T - T_ls)) <= 1e-8
     # the same route through the real-space solver of this library

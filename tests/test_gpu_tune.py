@@ -47,3 +47,35 @@ def test_every_tuned_shape_matches_oracle(gpu_lib, plane):
         T, d = P.negf_transmission(op, wire.energies, n_cols=384, tol=1e-12, block_width=32)
         assert d.status == 0
         assert np.max(np.abs(T - T_ref)) <= 1e-8, (target, plane)
+
+
+
+@pytest.mark.parametrize("shape", [(9, 7), (13, 40), (1, 1)])
+def test_both_stencil_kernels_on_planes_off_the_wave_size(gpu_lib, shape):
+    """Planes of 63, 520 and 1 points: the whole-plane kernel pads its block
+    to whole waves (1, 56 and 63 padding lanes), the row-tiled kernel runs
+    each as one tile.  Both give the oracle's partial T(E) over 16 source
+    columns in the middle of the right CAP."""
+    import paper_1401_0782_amd as P
+    from workloads import make_custom, rhs_columns
+
+    nx, ny = shape
+    h = 0.5
+    if nx > 1:
+        n_cap = 6
+        w = make_custom(nx, ny, 24, h, 2, n_cap, np.linspace(0.3, 1.1, 2),
+                        wells=[((nx + 1) * h / 2, (ny + 1) * h / 2, 25 * h / 2, 0.5)])
+    else:  # a chain: its band starts at 10 Ha
+        n_cap = 40
+        w = make_custom(1, 1, 120, h, 2, n_cap, np.linspace(10.3, 13.0, 2), w0=0.5)
+    op = P.operator_from_wire(w)
+    c0 = (n_cap // 2) * nx * ny
+    src = rhs_columns(w)[c0:c0 + 16]
+    T_ref = np.array([O.column_transmissions(w, E, src).sum() for E in w.energies])
+    assert T_ref.max() > 1e-3
+    for plane in (1, 0):
+        P.negf_set_launch_shape(op, 16, 256, plane)
+        T, d = P.negf_transmission(op, w.energies, n_cols=16, col_begin=c0, col_count=16,
+                                   tol=1e-12, block_width=16)
+        assert d.status == 0
+        assert np.max(np.abs(T - T_ref)) <= 1e-8, (plane, T, T_ref)
