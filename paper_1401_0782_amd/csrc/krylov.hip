@@ -384,7 +384,7 @@ __global__ __launch_bounds__(kT) void k_update_ms(
         for (int u = 0; u < U; ++u) {
             const int64_t i = base + (int64_t)u * kT;
             if (i < i1) {
-                qv[u] = qc[i];
+                qv[u] = ld_once<R>(qc + i);  // q is dead after this step
                 rv[u] = rc[i];
             }
         }

@@ -17,6 +17,18 @@ template <> struct cplx_of<double> { using type = double2; };
 template <> struct cplx_of<float> { using type = float2; };
 template <typename R> using cplx_t = typename cplx_of<R>::type;
 
+// A complex element loaded with the non-temporal hint: for streams read once
+// and dead afterwards, so that they do not displace data still to be reused
+template <typename R>
+__device__ __forceinline__ cplx_t<R> ld_once(const cplx_t<R>* p) {
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    const v2 t = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    cplx_t<R> o;
+    o.x = t.x;
+    o.y = t.y;
+    return o;
+}
+
 __host__ __device__ inline double2 mk(double a, double b) { return make_double2(a, b); }
 __host__ __device__ inline double2 cadd(double2 a, double2 b) { return mk(a.x + b.x, a.y + b.y); }
 __host__ __device__ inline double2 csub(double2 a, double2 b) { return mk(a.x - b.x, a.y - b.y); }

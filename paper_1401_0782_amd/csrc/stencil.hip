@@ -596,7 +596,7 @@ __global__ __launch_bounds__(1024) void k_cocg_plane(
         const int zc = min(max(zz, 0), nz - 1);
         const int64_t gi = co + (int64_t)zc * plane + col_off;
         if (FUSED) rv = r[gi];
-        pv = pin[gi];
+        pv = ld_once<R>(pin + gi);  // p_{k-1} is dead after this step
     };
 
     for (int k = tid; k < 2 * pitch * lrows; k += blockDim.x) {
