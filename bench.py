@@ -40,10 +40,11 @@ KERNEL_SRC = ROOT / "paper_1401_0782_amd" / "csrc" / "stencil.hip"
 KERNELS = {1: "k_cocg_plane<6,double,true>", 0: "k_cocg_apply<6,double,1024,true>"}
 
 
-def _traffic_from_profile(kernel):
-    """HBM bytes per launch of the fused stencil kernel from the committed
-    rocprofv3 counter summary, or None if missing, taken on other source or on
-    the other stencil kernel."""
+def _traffic_from_profile(kernel, shape):
+    """HBM bytes over algorithmic bytes of the fused stencil kernel from the
+    committed rocprofv3 counter summary at this launch shape (wg_target,
+    plane_kernel), or None if missing, taken on other source, on the other
+    stencil kernel or at another shape."""
     if not COUNTERS.exists():
         return None, None
     fields = {}
@@ -56,11 +57,16 @@ def _traffic_from_profile(kernel):
         return None, "counters predate the current stencil source"
     if fields.get("kernel") != kernel:
         return None, f"counters were taken on {fields.get('kernel')}, this run used {kernel}"
+    tag = f"{shape[0]},{shape[1]}"
+    key = ("traffic_over_algorithmic" if fields.get("launch_shape") == tag
+           else f"traffic_over_algorithmic_at_{shape[0]}_{shape[1]}")
+    if key not in fields:
+        return None, f"no counters at launch shape {tag}"
     try:
         # measured with every column of the block active; per-launch traffic of
         # the timed run scales with its (smaller) average active-column count
-        return float(fields["traffic_over_algorithmic"]), None
-    except (KeyError, ValueError):
+        return float(fields[key]), None
+    except ValueError:
         return None, None
 
 
@@ -391,7 +397,7 @@ def main():
     solves = args.steps * args.block * n_e
     value = solves / elapsed
     achieved = mv_b / mv_s / 1e9 if mv_s > 0 else None
-    ratio, why = _traffic_from_profile(kernel)
+    ratio, why = _traffic_from_profile(kernel, (tuned["wg_target"], tuned["plane_kernel"]))
     traffic = ratio * mv_b / max(1, mv_n) if ratio else None
     roofline = {
         "bound": "hbm",

@@ -29,6 +29,16 @@ __device__ __forceinline__ cplx_t<R> ld_once(const cplx_t<R>* p) {
     return o;
 }
 
+// A complex element stored with the non-temporal hint
+template <typename R>
+__device__ __forceinline__ void st_once(cplx_t<R>* p, const cplx_t<R>& v) {
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    v2 t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, reinterpret_cast<v2*>(p));
+}
+
 __host__ __device__ inline double2 mk(double a, double b) { return make_double2(a, b); }
 __host__ __device__ inline double2 cadd(double2 a, double2 b) { return mk(a.x + b.x, a.y + b.y); }
 __host__ __device__ inline double2 csub(double2 a, double2 b) { return mk(a.x - b.x, a.y - b.y); }

@@ -645,7 +645,7 @@ __global__ __launch_bounds__(1024) void k_cocg_plane(
             const int64_t gz = co + (int64_t)min(z, nz - 1) * plane + col_off;
             if (FUSED) {
                 cplx_t<R>* dst = live ? pout + gz : my_sink;
-                *dst = xi;
+                st_once<R>(dst, xi);  // p_k: next read one whole step later
             }
             __syncthreads();
             const R dr = (R)(e_c - v_cur);
@@ -665,7 +665,7 @@ __global__ __launch_bounds__(1024) void k_cocg_plane(
             o.x = ax;
             o.y = ay;
             cplx_t<R>* ydst = live ? y + gz : my_sink;
-            *ydst = o;
+            st_once<R>(ydst, o);  // q: read once, by the update
             if (FUSED) {
                 const double dx = (double)xi.x * ax - (double)xi.y * ay;
                 const double dy = (double)xi.x * ay + (double)xi.y * ax;
