@@ -1,0 +1,88 @@
+"""Host logic of bench.py that needs no GPU: the counter summary is used only
+for the stencil source, kernel and launch shape it was taken on, and runs on
+more than one GPU are refused."""
+
+import pathlib
+import subprocess
+import sys
+
+import pytest
+
+ROOT = pathlib.Path(__file__).resolve().parents[1]
+sys.path.insert(0, str(ROOT))
+
+import bench  # noqa: E402
+
+KERNEL = "k_cocg_plane<6,double,true>"
+
+
+def _fields():
+    out = {}
+    for line in bench.COUNTERS.read_text().splitlines():
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            out[k.strip()] = v.strip()
+    return out
+
+
+def test_committed_counters_are_used_only_for_their_source():
+    import hashlib
+
+    f = _fields()
+    ratio, why = bench._traffic_from_profile(KERNEL, (192, 1))
+    src = hashlib.sha256(bench.KERNEL_SRC.read_bytes()).hexdigest()[:16]
+    if f["stencil_src_sha256_16"] != src:
+        # the source changed after the counters were taken: no traffic figure
+        assert ratio is None and "predate" in why
+        return
+    assert why is None, why
+    assert f["launch_shape"] == "192,1"
+    assert ratio == pytest.approx(float(f["traffic_over_algorithmic"]))
+    # HBM bytes are at least the algorithmic bytes, and not wildly above
+    assert 1.0 <= ratio < 1.3
+
+
+@pytest.fixture
+def matched(monkeypatch, tmp_path):
+    """The committed counter summary, re-keyed to a stand-in stencil source so
+    that the checks below hold whatever the source is now."""
+    import hashlib
+
+    src = tmp_path / "stencil.hip"
+    src.write_text("// stand-in source\n")
+    old_hash = _fields()["stencil_src_sha256_16"]
+    counters = tmp_path / "counters.txt"
+    counters.write_text(bench.COUNTERS.read_text().replace(
+        old_hash, hashlib.sha256(src.read_bytes()).hexdigest()[:16]))
+    monkeypatch.setattr(bench, "KERNEL_SRC", src)
+    monkeypatch.setattr(bench, "COUNTERS", counters)
+    return src
+
+
+def test_ratio_follows_the_tuned_shape(matched):
+    f = _fields()
+    r192, why = bench._traffic_from_profile(KERNEL, (192, 1))
+    assert why is None and r192 == pytest.approx(float(f["traffic_over_algorithmic"]))
+    # HBM bytes are at least the algorithmic bytes, and not wildly above
+    assert 1.0 <= r192 < 1.3
+    r256, why = bench._traffic_from_profile(KERNEL, (256, 1))
+    assert why is None and r256 == pytest.approx(float(f["traffic_over_algorithmic_at_256_1"]))
+    # four z-chunks re-read more halo planes than three
+    assert r256 > r192
+    r, why = bench._traffic_from_profile(KERNEL, (128, 1))
+    assert r is None and "128,1" in why
+
+
+def test_other_kernel_or_source_gives_no_traffic(matched):
+    r, why = bench._traffic_from_profile("k_cocg_apply<6,double,1024,true>", (192, 1))
+    assert r is None and "k_cocg_plane" in why
+    matched.write_text(matched.read_text() + "// changed\n")
+    r, why = bench._traffic_from_profile(KERNEL, (192, 1))
+    assert r is None and "predate" in why
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, str(ROOT / "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
