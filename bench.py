@@ -321,7 +321,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: this library has no multi-GPU path "
               "(columns would shard across GPUs with one all-reduce of T(E)); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
