@@ -316,6 +316,10 @@ def main():
                     help="instead of the headline step, time other workloads and forms: "
                          + ", ".join(ROWS))
     args = ap.parse_args()
+    if args.rows:
+        bad = [r for r in args.rows.split(",") if r not in ROWS]
+        if bad:
+            ap.error(f"unknown rows {', '.join(bad)}: choose from {', '.join(ROWS)}")
     if args.oracle_iterations:
         measure_oracle_iterations([int(v) for v in args.oracle_iterations.split(",")])
         return

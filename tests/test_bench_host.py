@@ -86,3 +86,10 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert p.returncode == 2
     assert "one GPU" in p.stderr
+
+
+def test_unknown_rows_are_refused_before_any_device_work():
+    p = subprocess.run([sys.executable, str(ROOT / "bench.py"), "--rows", "small,bogus"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "bogus" in p.stderr and "spectral" in p.stderr
