@@ -153,8 +153,15 @@ typedef struct negf_op negf_op;
  *   cap_right_z nz values W_R(z) >= 0, nonzero only on trailing planes
  * Requirements (else NEGF_E_INVALID_ARG): the two supports are disjoint,
  * each is a contiguous run of at least R planes touching its wall (this
- * makes A(E) nonsingular for real E without projectors), and no projector
- * point lies on a CAP plane.  *out receives a new op; free with negf_destroy. */
+ * makes A(E) nonsingular for real E without projectors), no projector
+ * point lies on a CAP plane, and nx is at most the widest x-row the stencil
+ * tile holds: min(1024, 163840 / (32 (2R+1)) - 2R), i.e. 1024, 1020, 725,
+ * 560, 455, 381 for R = 1..6 (one thread per point of a row, and one row
+ * with its radius-R halo in a double-buffered FP64 LDS tile of 160 KB);
+ * the tile of t rows then needs 32 (t + 2R)(nx + 2R) <= 163840 bytes, with
+ * t = ny for planes of at most 1024 points, else min(ny, 1024 / nx), which
+ * excludes only narrow, tall planes (such as 2 x 512 or 3 x 400 at R = 6).
+ * *out receives a new op; free with negf_destroy. */
 negf_status negf_build_operator(const negf_grid* g, int32_t stencil_radius,
                                 const double* v_local, const negf_kb* kb,
                                 const double* cap_left_z, const double* cap_right_z,

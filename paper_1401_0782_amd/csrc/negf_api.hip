@@ -222,6 +222,27 @@ static negf_status build_impl(const negf_grid* g, int32_t R, const double* v, co
         set_error("stencil radius %d outside 1..6", R);
         return NEGF_E_INVALID_ARG;
     }
+    // the fused stencil step gives each point of an x-row a thread and stages
+    // at least one row, with its radius-R halo, in a double-buffered FP64 LDS
+    // tile of at most 160 KB
+    const int max_nx = std::min(1024, 163840 / (32 * (2 * R + 1)) - 2 * R);
+    if (g->nx > max_nx) {
+        set_error("nx = %d exceeds %d, the widest x-row the stencil tile holds at radius %d",
+                  g->nx, max_nx, R);
+        return NEGF_E_INVALID_ARG;
+    }
+    {
+        // the tile itself: a whole plane of at most 1024 points, else
+        // 1024 / nx rows (256 / nx for planes of at most 256 points)
+        const int64_t pts = (int64_t)g->nx * g->ny;
+        const int64_t rows = pts <= 1024 ? g->ny : std::min<int64_t>(g->ny, 1024 / g->nx);
+        const int64_t lds = (rows + 2 * R) * 2 * (g->nx + 2 * R) * 16;
+        if (lds > 163840) {
+            set_error("a %d x %d plane needs a %lld-byte stencil tile in LDS (at most 163840)",
+                      g->nx, g->ny, (long long)lds);
+            return NEGF_E_INVALID_ARG;
+        }
+    }
     const int64_t N = (int64_t)g->nx * g->ny * g->nz;
     if (N > (int64_t)1 << 31) {
         set_error("grid too large");

@@ -163,3 +163,52 @@ def test_opts_layout_matches_header():
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     fields = re.findall(r"\b(int32_t|double|void\*)\s+([a-z_]+);", body)
     assert [f[1] for f in fields] == [f[0] for f in _abi.negf_opts._fields_]
+
+
+@pytest.mark.parametrize("R,max_nx", [(1, 1024), (2, 1020), (3, 725), (4, 560), (5, 455), (6, 381)])
+def test_x_rows_wider_than_the_stencil_tile_rejected(R, max_nx):
+    """One x-row with its radius-R halo must fit the double-buffered FP64 LDS
+    tile (160 KB), one thread per point: wider grids are refused by the
+    build, before any device work; the widest admitted row passes that
+    check."""
+    from paper_1401_0782_amd import NegfError
+    from paper_1401_0782_amd._abi import NEGF_E_INVALID_ARG
+
+    assert max_nx == min(1024, 163840 // (32 * (2 * R + 1)) - 2 * R)
+    nz = 2 * R + 4
+    cap_l = np.zeros(nz)
+    cap_l[:R] = 0.1
+    cap_r = cap_l[::-1].copy()
+    kw = dict(ny=1, nz=nz, stencil_radius=R, cap_left_z=cap_l, cap_right_z=cap_r)
+    with pytest.raises(NegfError) as ei:
+        _build(nx=max_nx + 1, v_local=np.zeros((max_nx + 1) * nz), **kw)
+    assert ei.value.status == NEGF_E_INVALID_ARG and "widest x-row" in str(ei.value)
+    try:  # without a device this fails later, for another reason
+        _build(nx=max_nx, v_local=np.zeros(max_nx * nz), **kw)
+    except NegfError as e:
+        assert "widest x-row" not in str(e)
+
+
+@pytest.mark.parametrize("nx,ny,ok", [(2, 512, False), (3, 400, False), (4, 256, True),
+                                      (32, 32, True), (40, 40, True), (64, 64, True)])
+def test_planes_whose_stencil_tile_overflows_lds_rejected(nx, ny, ok):
+    """At R = 6 the tile of a narrow, tall plane (whole plane, or 1024 / nx
+    rows) with its halo exceeds 160 KB of LDS: refused before device work.
+    Square cross-sections pass the check."""
+    from paper_1401_0782_amd import NegfError
+    from paper_1401_0782_amd._abi import NEGF_E_INVALID_ARG
+
+    R, nz = 6, 16
+    cap_l = np.zeros(nz)
+    cap_l[:R] = 0.1
+    kw = dict(nx=nx, ny=ny, nz=nz, stencil_radius=R, v_local=np.zeros(nx * ny * nz),
+              cap_left_z=cap_l, cap_right_z=cap_l[::-1].copy())
+    if not ok:
+        with pytest.raises(NegfError) as ei:
+            _build(**kw)
+        assert ei.value.status == NEGF_E_INVALID_ARG and "stencil tile in LDS" in str(ei.value)
+        return
+    try:  # without a device this fails later, for another reason
+        _build(**kw)
+    except NegfError as e:
+        assert "stencil tile" not in str(e) and "widest x-row" not in str(e)
