@@ -243,6 +243,63 @@ def test_spectral_route_degenerate_wire():
     assert np.max(np.abs(Td - Tsp)) < 1e-10
 
 
+@pytest.fixture(scope="module")
+def band_wire():
+    """A 2 x 2 x 60 wire with one shallow well and 20-plane CAPs (W0 = 0.5 Ha),
+    its energy window inside the first transverse band (T close to 1), the
+    full T from dense inversion, and the eigenvalues of H - iW."""
+    nx, ny, h, R = 2, 2, 0.5, 2
+    th = O.transverse_thresholds(nx, ny, h, R)[0]
+    w = make_custom(nx, ny, 60, h, R, 20, np.linspace(th + 0.3, th + 0.8, 6),
+                    wells=[(0.75, 0.75, 15.25, 0.5)], w0=0.5)
+    Tfull = O.transmission(w, method="dense")
+    wl, wr = O.cap_diagonals(w)
+    eps = np.linalg.eigvals(O.hamiltonian(w).toarray() - 1j * np.diag(wl + wr))
+    return w, Tfull, eps
+
+
+def _window_distance(w, eps):
+    lo, hi = w.energies.min(), w.energies.max()
+    return np.maximum(np.maximum(lo - eps.real, eps.real - hi), 0.0)
+
+
+def test_spectral_truncation_paper_criterion(band_wire):
+    """Sec. II.C after Eq. 13: eigenpairs with |E - eps_j|^2 >> Gamma_0^2 may be
+    dropped.  Keeping every pole within 4 W0 of the window (|E - eps|^2 >= 16
+    W0^2 dropped) must reproduce the full T inside the window (dense route)
+    to 2e-3 of T ~ 1 (measured 6.7e-4); the fraction keep = n/N_r keeps exactly
+    those poles, since nearness to the window's middle orders them the same
+    way.  A selection by the wrong end (farthest poles), or a dropped pole
+    near the window, fails the bound."""
+    w, Tfull, eps = band_wire
+    assert Tfull.min() > 0.9
+    W0 = 0.5
+    d = _window_distance(w, eps)
+    n = int(np.sum(d <= 4 * W0))
+    assert 0 < n < len(eps) // 4
+    Tp = O.transmission_spectral(w, keep=n / len(eps))
+    assert np.max(np.abs(Tp - Tfull)) < 2e-3
+
+
+def test_spectral_truncation_drops_near_poles_fail(band_wire):
+    """The pole-like artefacts the paper warns of: keeping only the poles
+    inside the window, or within W0/2 of it, misses T by more than 0.1."""
+    w, Tfull, eps = band_wire
+    d = _window_distance(w, eps)
+    for radius in (0.0, 0.25):
+        n = int(np.sum(d <= radius))
+        Tp = O.transmission_spectral(w, keep=n / len(eps))
+        assert np.max(np.abs(Tp - Tfull)) > 0.1, radius
+
+
+def test_spectral_truncation_converges_as_p_to_1(band_wire):
+    """T_p -> T as the kept fraction p -> 1: within 1e-4 at p = 0.9, and the
+    route is exact (to rounding) at p = 1."""
+    w, Tfull, _ = band_wire
+    assert np.max(np.abs(O.transmission_spectral(w, keep=0.9) - Tfull)) < 1e-4
+    assert np.max(np.abs(O.transmission_spectral(w, keep=1.0) - Tfull)) < 1e-10
+
+
 # ---------------------------------------------------------------- gradient
 def test_gradient_dense_matches_fd(small_wire):
     E = 0.8
