@@ -6,8 +6,10 @@ energies in [0.05, 0.8] Ha of the 32 x 32 x 192 wire (h = 0.4 bohr, radius-6
 stencil, 20 seeded Gaussian atoms with s+p separable projectors, 16-plane
 quartic absorbing regions), i.e. 16,384 G-column x energy solves reduced to
 the shard's partial T(E), FP64, relative residual 1e-10 per (column, energy).
-Consecutive steps take consecutive column shards.  Inputs are synthetic
-(seeded) and resident on the GPU when the timed region starts.
+The timed steps take 64-column shards spread evenly over the 256 shards of
+the right absorbing region (all 16 of its planes, innermost to outermost);
+stored oracle samples that fall in a timed shard are checked.  Inputs are
+synthetic (seeded) and resident on the GPU when the timed region starts.
 
 Printed: one JSON line with the solves/s, the roofline entry of the dominant
 kernel (the fused stencil step) and the CPU oracle baseline.
@@ -33,7 +35,11 @@ TOL = 1e-10
 # the stencil launches of every TIME_EVERY-th chunk of 256 iterations are timed
 # with HIP events (run eagerly); the other chunks replay as graphs
 TIME_EVERY = 8
+# the launch shape every default run uses (stencil work-groups per launch,
+# whole-plane kernel); --tune asks the library's autotuner instead
+LAUNCH_SHAPE = (192, 1)
 COUNTERS = ROOT / "profiles" / "stencil_wire32x32x192_counters.txt"
+GOLDEN = ROOT / "tests" / "golden" / "wire32x32x192_samples.json"
 KERNEL_SRC = ROOT / "paper_1401_0782_amd" / "csrc" / "stencil.hip"
 
 
@@ -308,7 +314,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--launch-shape", type=str, default=None, metavar="WG_TARGET,PLANE",
-                    help="fix the stencil launch shape instead of tuning it (profiler runs)")
+                    help="stencil launch shape (default %d,%d)" % LAUNCH_SHAPE)
+    ap.add_argument("--tune", action="store_true",
+                    help="pick the launch shape with the library's autotuner instead")
     ap.add_argument("--oracle-iterations", type=str, default=None, metavar="E_IDX,...",
                     help="CPU only: run the oracle's BiCGSTAB to completion at these energy "
                          "indices and print the iteration counts (the CPU baseline's scale)")
@@ -352,23 +360,32 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
 
-    # launch shape (z-chunking, stencil kernel) for this block width, picked once
-    # by the library's autotuner before any timing (or fixed for profiler runs,
-    # whose timing would mislead the tuner)
-    if args.launch_shape:
-        tgt, plane = (int(v) for v in args.launch_shape.split(","))
+    # launch shape (z-chunking, stencil kernel): fixed, so that every run, its
+    # kernel statistics and its counters share one shape (the autotuner's
+    # choice between close candidates varies from run to run)
+    if args.tune:
+        tuned = P.negf_tune(op, wire.energies, block_width=args.block)
+    else:
+        tgt, plane = ((int(v) for v in args.launch_shape.split(",")) if args.launch_shape
+                      else LAUNCH_SHAPE)
         P.negf_set_launch_shape(op, args.block, tgt, plane)
         tuned = {"block_width": args.block, "wg_target": tgt, "plane_kernel": plane}
-    else:
-        tuned = P.negf_tune(op, wire.energies, block_width=args.block)
     plane_fits = wire.nx * wire.ny <= 1024
     kernel = KERNELS[1 if (tuned["plane_kernel"] != 0 and plane_fits) else 0]
     print(f"tuned launch shape: block {tuned['block_width']}, stencil work-groups "
           f"{tuned['wg_target']}, whole-plane kernel {tuned['plane_kernel']}",
           file=sys.stderr, flush=True)
 
-    def step(i):
-        c0 = (i * args.block) % n_src
+    # timed shards spread evenly over the right absorbing region; warm-up
+    # shards in between
+    n_blk = n_src // args.block
+    timed_blk = [int(b) for b in np.round(np.linspace(0, n_blk - 1, args.steps))]
+    warm_blk = [int(b) for b in np.round(np.linspace(0, n_blk - 1, args.warmup + 2))[1:-1]]
+    golden = json.loads(GOLDEN.read_text())["samples"] if GOLDEN.exists() else []
+    checked = []
+
+    def step(blk):
+        c0 = blk * args.block
         T, d = P.negf_transmission(op, wire.energies, n_cols=args.block, check=False,
                                    time_matvec=TIME_EVERY, col_begin=c0, col_count=args.block,
                                    block_width=args.block, tol=TOL, max_iter=args.max_iter)
@@ -378,8 +395,8 @@ def main():
         return T, d
 
     for i in range(args.warmup):
-        step(i)
-        print(f"warmup step {i} done", file=sys.stderr, flush=True)
+        step(warm_blk[i])
+        print(f"warmup step {i} done (shard {warm_blk[i]})", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mv_s = mv_b = 0.0
@@ -387,14 +404,18 @@ def main():
     not_conv = 0
     iters = 0
     for i in range(args.steps):
-        T, d = step(args.warmup + i)
+        T, d = step(timed_blk[i])
+        for smp in golden:
+            if smp["col"] // args.block == timed_blk[i]:
+                t = float(d.t_col[smp["e_index"], smp["col"] - timed_blk[i] * args.block])
+                checked.append((smp["col"], smp["e_index"], abs(t - smp["t_col"]), smp["t_col"]))
         mv_s += d.extra["matvec_seconds"]
         mv_b += d.extra["matvec_bytes"]
         mv_n += d.extra["matvec_launches"]
         not_conv += d.n_not_converged
         iters += d.total_iters
-        print(f"step {i} done ({d.seconds:.2f} s, {d.total_iters} column-iterations)",
-              file=sys.stderr, flush=True)
+        print(f"step {i} done (shard {timed_blk[i]}, {d.seconds:.2f} s, "
+              f"{d.total_iters} column-iterations)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -412,7 +433,8 @@ def main():
         "traffic": traffic,  # HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)
         "kernel": kernel + " (fused p = r + beta p, stencil + potential + CAP apply, p^T q partials)",
         "launches": mv_n,
-        "timed_sample": f"stencil launches of every {TIME_EVERY}th chunk of 256 iterations, "
+        "timed_sample": f"stencil launches of every {TIME_EVERY}th chunk of 256 iterations "
+                        f"(launched eagerly, the shift GEMM overlapping as in the other chunks), "
                         f"{mv_n} launches over the timed steps",
         "avg_launch_us": 1e6 * mv_s / max(1, mv_n),
         "bytes_per_launch": mv_b / max(1, mv_n),
@@ -440,6 +462,10 @@ def main():
             "launch_shape": {k: tuned[k] for k in ("block_width", "wg_target", "plane_kernel")},
             "column_iterations": iters,
             "not_converged": not_conv,
+            "timed_shards": timed_blk,
+            "oracle_samples_checked": [
+                {"col": c, "e_index": e, "abs_dt": dt, "t_oracle": t} for c, e, dt, t in checked],
+            "max_abs_dt_vs_oracle": max((c[2] for c in checked), default=None),
         },
         "roofline": roofline,
     }

@@ -71,6 +71,13 @@ negf_status hip_fail(hipError_t e, const char* what, int line) {
 // process fail (exercises the out-of-memory path without exhausting HBM).
 static std::atomic<long> g_alloc_count{0};
 
+// Device allocation and release, and the capture and instantiation of the
+// chunk graphs, take this lock.  Host threads of the junction batch each
+// drive their own stream; hipFree synchronises the device and hipMalloc may
+// too, so neither may run while another thread has a stream in capture or
+// a graph half-instantiated.
+static std::mutex g_device_mu;
+
 static negf_status dev_alloc(void** p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) bytes = 256;
@@ -81,6 +88,7 @@ static negf_status dev_alloc(void** p, size_t bytes) {
             return NEGF_E_OUT_OF_MEMORY;
         }
     }
+    std::lock_guard<std::mutex> lock(g_device_mu);
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -91,10 +99,16 @@ static negf_status dev_alloc(void** p, size_t bytes) {
     return NEGF_OK;
 }
 
+static void dev_free(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(g_device_mu);
+    (void)hipFree(p);
+}
+
 negf_status ws_get(negf_op* op, int slot, size_t bytes, void** out) {
     Buffer& b = op->bufs[slot];
     if (b.bytes < bytes) {
-        if (b.ptr) (void)hipFree(b.ptr);
+        if (b.ptr) dev_free(b.ptr);
         b.ptr = nullptr;
         b.bytes = 0;
         CHK(dev_alloc(&b.ptr, bytes));
@@ -190,10 +204,8 @@ static void free_op(negf_op* op) {
     if (op->side_stream) (void)hipStreamSynchronize(op->side_stream);
     void* ptrs[] = {op->d_v, op->d_wz, op->d_wl, op->d_wr, op->kb.off, op->kb.idx, op->kb.val,
                     op->kb.valf, op->kb.e, op->kb.pts, op->kb.pt_off, op->kb.pt_proj, op->kb.pt_val, op->kb.slot};
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
-    for (auto& b : op->bufs)
-        if (b.ptr) (void)hipFree(b.ptr);
+    for (void* p : ptrs) dev_free(p);
+    for (auto& b : op->bufs) dev_free(b.ptr);
     if (op->own_stream) (void)hipStreamDestroy(op->own_stream);
     if (op->side_stream) (void)hipStreamDestroy(op->side_stream);
     delete op;
@@ -357,6 +369,9 @@ static negf_status build_impl(const negf_grid* g, int32_t R, const double* v, co
     HIPCHK(hipStreamCreateWithFlags(&op->own_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&op->side_stream, hipStreamNonBlocking));
     op->bufs.resize(WS_COUNT);
+    // the large-LDS opt-in of the stencil kernels this grid can take happens
+    // here, never inside a stream capture
+    prepare_stencil_kernels(op);
     return NEGF_OK;
 }
 
@@ -588,11 +603,26 @@ struct MatvecTimer {
 struct ChunkGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipStream_t launched_on = nullptr;  // the last replay's stream
     int timer_pairs = 0;
     bool failed = false;
     ~ChunkGraph() {
+        // an error return can leave a replay in flight
+        if (launched_on) (void)hipStreamSynchronize(launched_on);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+// Synchronises the given streams when it goes out of scope: declared after
+// the graphs and events of a solver driver, it runs first on every return
+// path, so that nothing those objects own is released while work that uses
+// it may still be queued.
+struct DrainGuard {
+    hipStream_t a, b;
+    ~DrainGuard() {
+        if (a) (void)hipStreamSynchronize(a);
+        if (b) (void)hipStreamSynchronize(b);
     }
 };
 
@@ -622,6 +652,7 @@ static negf_status run_chunk(ChunkGraph& cg, bool use_graph, hipStream_t s, Matv
     if (tm->on && tm->active) use_graph = false;
     if (use_graph && !cg.failed && !cg.exec) {
         CHK(tm->flush());
+        std::lock_guard<std::mutex> lock(g_device_mu);
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
             const negf_status st = issue();
             hipGraph_t g = nullptr;
@@ -648,6 +679,7 @@ static negf_status run_chunk(ChunkGraph& cg, bool use_graph, hipStream_t s, Matv
         }
     }
     if (use_graph && cg.exec) {
+        cg.launched_on = s;
         HIPCHK(hipGraphLaunch(cg.exec, s));
         tm->used = cg.timer_pairs;
         return NEGF_OK;
@@ -797,6 +829,7 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
     std::vector<double> h_colw(w, 0.0);
     int launches = 0;
     ChunkGraph cg;
+    DrainGuard drain{s, side};
     const bool use_graph = graphs_enabled();
     int running = w;  // columns still iterating at the chunk start
     while (true) {
@@ -809,13 +842,12 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
         const int nblk_f = fused_partials(op, w_geom);
         int* kstart = kstart_buf[(launches / ch) & 1];
         // timing: every period-th chunk runs eagerly with its stencil launches
-        // bracketed by events, the others replay as graphs; the GEMM that would
-        // overlap a timed chunk stays on the main stream, so that every timed
-        // launch has the device to itself
+        // bracketed by events, the others replay as graphs; the GEMM overlaps
+        // timed and untimed chunks alike, so that the timed launches share the
+        // device as all the others do
         const int chunk_index = launches / ch;
         tm->active = tm->on && chunk_index % tm->period == 0;
-        const bool next_timed = tm->on && (chunk_index + 1) % tm->period == 0;
-        hipStream_t gemm_stream = next_timed ? s : side;
+        hipStream_t gemm_stream = side;
         HIPCHK(hipMemcpyAsync(kstart, st.k, w * sizeof(int), hipMemcpyDeviceToDevice, s));
         auto issue = [&]() -> negf_status {
             for (int it = 0; it < steps; ++it) {
@@ -1051,6 +1083,7 @@ static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, c
     std::vector<int> h_done(w), h_odone(w), h_k(w), iters(w, 0), refine(w, 0);
     int outer = 0;
     ChunkGraph cg;
+    DrainGuard drain{s, nullptr};
     const bool use_graph = graphs_enabled();
     const double inner_tol = (sizeof(R) == 8) ? 0.5 * d.tol : 2e-6;
     while (true) {
@@ -1618,7 +1651,7 @@ static void release_workspace(negf_op* op) {
     (void)hipStreamSynchronize(op->own_stream);
     (void)hipStreamSynchronize(op->side_stream);
     for (auto& b : op->bufs) {
-        if (b.ptr) (void)hipFree(b.ptr);
+        dev_free(b.ptr);
         b.ptr = nullptr;
         b.bytes = 0;
     }
@@ -1807,7 +1840,7 @@ extern "C" negf_status negf_current(int32_t n_e, const double* energies, const d
         return NEGF_OK;
     };
     st = run();
-    (void)hipFree(buf);
+    dev_free(buf);
     return st;
 }
 
@@ -1912,7 +1945,7 @@ static negf_status spectral_impl(negf_op* op, int32_t n_r, const negf_c64* eps,
     };
     const negf_status st = run();
     (void)hipStreamSynchronize(s);
-    (void)hipFree(base);
+    dev_free(base);
     return st;
 }
 
@@ -2026,10 +2059,9 @@ extern "C" negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* op
     for (auto& th : threads) th.join();
     (void)hipDeviceSynchronize();
     for (auto& v : to_free)
-        for (void* ptr : v) (void)hipFree(ptr);
+        for (void* ptr : v) dev_free(ptr);
     for (auto& pool : pools)
-        for (auto& b : pool)
-            if (b.ptr) (void)hipFree(b.ptr);
+        for (auto& b : pool) dev_free(b.ptr);
     negf_status first = NEGF_OK;
     for (int i = 0; i < n_ops; ++i) {
         if (status) status[i] = st[i];

@@ -188,6 +188,9 @@ void launch_cocg_apply(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* p
                        const int* kit, const double2* beta, double2* part, double2* d_kbc,
                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, bool kb_scatter = true,
                        int w_geom = 0);
+// opts in the fused stencil kernels this op's grid can launch to more than
+// 64 KB of LDS (once per kernel and device; called when the op is built)
+void prepare_stencil_kernels(const negf_op* op);
 // partials per column of the fused kernel when its z-chunking is chosen for w
 // running columns (more chunks per column for fewer columns)
 int fused_partials(const negf_op* op, int w);

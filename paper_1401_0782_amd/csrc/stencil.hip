@@ -785,7 +785,44 @@ void fused_launch(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin, c
         go(k_cocg_apply<RAD, R, 1024, FUSED>, 1024);
 }
 
+template <int RAD, typename R>
+void prepare_fused(const negf_op* op) {
+    const int pts = op->nx * op->ny;
+    // whole-plane kernel: the geometry does not depend on the z-chunking
+    if (pts <= 1024) {
+        const size_t lds = 2 * (size_t)(op->nx + 2 * RAD) * (op->ny + 2 * RAD) * sizeof(cplx_t<R>);
+        if (lds > 65536) allow_large_lds((const void*)k_cocg_plane<RAD, R, true>);
+    }
+    // row-tiled kernel (also reachable for small planes through the tuner)
+    for (int nt : {256, 1024}) {
+        if (nt == 256 && pts > 256) continue;
+        const int ty = std::min(op->ny, nt / op->nx);
+        if (ty < 1) continue;
+        const size_t lds = 2 * (size_t)(op->nx + 2 * RAD) * (ty + 2 * RAD) * sizeof(cplx_t<R>);
+        if (lds <= 65536) continue;
+        if (nt == 256) allow_large_lds((const void*)k_cocg_apply<RAD, R, 256, true>);
+        else allow_large_lds((const void*)k_cocg_apply<RAD, R, 1024, true>);
+    }
+}
+
+template <int RAD>
+void prepare_radius(const negf_op* op) {
+    prepare_fused<RAD, double>(op);
+    prepare_fused<RAD, float>(op);
+}
+
 }  // namespace
+
+void prepare_stencil_kernels(const negf_op* op) {
+    switch (op->R) {
+        case 1: prepare_radius<1>(op); break;
+        case 2: prepare_radius<2>(op); break;
+        case 3: prepare_radius<3>(op); break;
+        case 4: prepare_radius<4>(op); break;
+        case 5: prepare_radius<5>(op); break;
+        default: prepare_radius<6>(op); break;
+    }
+}
 
 int fused_partials(const negf_op* op, int w) {
     switch (op->R) {

@@ -6,8 +6,9 @@ residual <= 1e-12) and stores t_j(E) = 4 W_R,j sum_{i in L} W_L,i |G_ij|^2
 (Eq. 7 with Gamma = 2W) plus G_jj, in tests/golden/wire32x32x192_samples.json.
 Only oracle/ and the input generator are used.
 
-usage: python tests/golden/make_wire32x32x192_samples.py COL:E [COL:E ...]
-(samples are merged into the existing file; each sample is one process)
+usage: python tests/golden/make_wire32x32x192_samples.py [--drop COL:E ...] COL:E [COL:E ...]
+(samples are merged into the existing file; each sample is one process;
+--drop removes a stored sample, e.g. one whose t_j is too small to inform)
 """
 
 import json
@@ -47,14 +48,19 @@ def one(spec):
 
 
 if __name__ == "__main__":
-    specs = [tuple(int(v) for v in a.split(":")) for a in sys.argv[1:]]
-    with mp.get_context("spawn").Pool(len(specs)) as pool:
-        results = pool.map(one, specs)
+    args = sys.argv[1:]
+    drop = {tuple(int(v) for v in args[i + 1].split(":")) for i, a in enumerate(args) if a == "--drop"}
+    specs = [tuple(int(v) for v in a.split(":")) for i, a in enumerate(args)
+             if a != "--drop" and (i == 0 or args[i - 1] != "--drop")]
+    results = []
+    if specs:
+        with mp.get_context("spawn").Pool(len(specs)) as pool:
+            results = pool.map(one, specs)
     data = json.loads(OUT.read_text()) if OUT.exists() else {
         "workload": "wire 32x32x192 h=0.4 R=6, 20 atoms + s,p KB, CAP 16 (make_wire(2))",
         "generator": "tests/golden/make_wire32x32x192_samples.py (oracle iterative route)",
         "samples": []}
-    keep = {(s["col"], s["e_index"]) for s in results}
+    keep = {(s["col"], s["e_index"]) for s in results} | drop
     data["samples"] = [s for s in data["samples"] if (s["col"], s["e_index"]) not in keep] + results
     OUT.write_text(json.dumps(data, indent=1) + "\n")
     print(json.dumps(results, indent=1))
