@@ -123,7 +123,11 @@ typedef struct {
  * (nx*ny*planes of the source CAP). */
 typedef struct {
     int32_t* iters;          /* Krylov iterations used for the item */
-    double* resid;           /* final relative residual (see negf_opts.tol) */
+    double* resid;           /* final relative residual: per-energy core, the FP64
+                                true residual ||b - A x|| / ||b||; multi-shift core,
+                                the COCG residual estimate ||r_k|| / (|pi_k| ||b||)
+                                at which the energy froze (that core never forms an
+                                energy's full-length iterate) */
     double* t_col;           /* per-column transmission t_j(E) */
     int32_t* item_status;    /* NEGF_ITEM_* */
     int64_t total_iters;     /* out: sum of Krylov iterations over runs */
@@ -140,6 +144,14 @@ typedef struct {
     double matvec_bytes;     /* out: algorithmic HBM bytes of those launches: per
                                 active column r and p_{k-1} read, p_k and q written
                                 (16 B per point in FP64, 8 B in FP32), plus V once */
+    double* optical_err;     /* per item, the optical theorem of the column
+                                g_j = A^-1 e_j (from A = E - H + iW, Eq. 4, H real):
+                                |sum_i W_i |g_ij|^2 + Im g_jj| / |Im g_jj| over both
+                                absorbing regions.  Requesting it makes the
+                                multi-shift core also keep the source side's rows
+                                (twice the kept rows) */
+    int32_t* refine_steps;   /* per item, outer refinement steps of the per-energy
+                                core (0 in the multi-shift core) */
 } negf_diag;
 
 typedef struct negf_op negf_op;
@@ -196,17 +208,23 @@ negf_status negf_transmission(negf_op* op, const negf_opts* opts, int32_t n_e,
                               const double* energies, double* T, negf_diag* diag);
 
 /* Batched T(E) over n_ops independent junctions (each its own operator, grid
- * and energy grid), submitted together so that the device overlaps them: the
- * junctions are taken largest-first by up to max_concurrent host workers, each
- * driving one junction at a time on that operator's own stream (the chunks of
- * iterations are HIP-graph replays).  Each op's workspace is released when its
- * junction finishes.  Equivalent to calling negf_transmission(ops[i], opts,
- * n_e[i], energies[i], T[i], NULL) for every i; the per-op results are
- * bit-identical to that.
- *   ops         n_ops operators (distinct; each used by one worker at a time)
+ * and energy grid), submitted together so that the device overlaps them.
+ * One host thread keeps up to max_concurrent junctions in flight, largest
+ * first, each on its operator's own stream: the multi-shift core advances in
+ * chunks of iterations (HIP-graph replays), and the thread queues a
+ * junction's next chunk as soon as its previous one has finished (event
+ * polling, no blocking wait on any one junction).  Junctions that do not run
+ * in the FP64 multi-shift core with every energy in one shift group (mixed
+ * precision, per-energy core, shift groups) are solved one at a time by the
+ * same thread.  Each op's workspace is released when its junction finishes.
+ * Equivalent to calling negf_transmission(ops[i], opts, n_e[i], energies[i],
+ * T[i], NULL) for every i; the per-op results are bit-identical to that.
+ *   ops         n_ops operators (distinct)
  *   n_e, energies, T   per-op energy counts, host energy arrays, host outputs
- *   status      n_ops host per-op negf_status codes (nullable)
- *   max_concurrent   workers (0 -> 4)
+ *   status      n_ops host per-op negf_status codes (nullable); a junction
+ *               whose items missed tol keeps its T and reports
+ *               NEGF_E_NOT_CONVERGED, like negf_transmission
+ *   max_concurrent   junctions in flight (0 -> 4)
  * Returns the first non-OK per-op status, or NEGF_OK. */
 negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* ops, const negf_opts* opts,
                                     const int32_t* n_e, const double* const* energies,

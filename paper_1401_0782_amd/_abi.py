@@ -64,7 +64,8 @@ class negf_diag(C.Structure):
                 ("total_iters", C.c_int64), ("n_not_converged", C.c_int32),
                 ("seconds", C.c_double), ("time_matvec", C.c_int32),
                 ("matvec_seconds", C.c_double), ("matvec_launches", C.c_int64),
-                ("matvec_bytes", C.c_double)]
+                ("matvec_bytes", C.c_double), ("optical_err", C.POINTER(C.c_double)),
+                ("refine_steps", C.POINTER(C.c_int32))]
 
 
 NEGF_TUNE_MAX = 64

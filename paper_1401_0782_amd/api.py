@@ -153,6 +153,8 @@ class Diagnostics:
     seconds: float = 0.0
     status: int = 0
     extra: dict = field(default_factory=dict)
+    refine_steps: Optional[np.ndarray] = None
+    optical_err: Optional[np.ndarray] = None
 
 
 def n_source_columns(op: Operator, cap_src) -> int:
@@ -160,11 +162,12 @@ def n_source_columns(op: Operator, cap_src) -> int:
 
 
 def negf_transmission(op: Operator, energies, n_cols: Optional[int] = None, check=True,
-                      time_matvec=False, **opts):
+                      time_matvec=False, optical=False, **opts):
     """T(E) (FP64) for the given energies.  n_cols (number of source columns
-    in the shard, see col_begin/col_count) enables the per-item diagnostics;
-    time_matvec brackets the stencil launches with HIP events (an int n > 1
-    times every n-th chunk of the multi-shift core)."""
+    in the shard, see col_begin/col_count) enables the per-item diagnostics
+    (optical=True adds the per-item optical-theorem error); time_matvec
+    brackets the stencil launches with HIP events (an int n > 1 times every
+    n-th chunk of the multi-shift core)."""
     energies = np.ascontiguousarray(energies, dtype=np.float64)
     n_e = energies.size
     T = np.zeros(n_e)
@@ -174,14 +177,18 @@ def negf_transmission(op: Operator, energies, n_cols: Optional[int] = None, chec
     if n_cols or time_matvec:
         nc = max(1, n_cols or 0)
         arrays = (np.zeros((n_e, nc), np.int32), np.zeros((n_e, nc)),
-                  np.zeros((n_e, nc)), np.zeros((n_e, nc), np.int32))
+                  np.zeros((n_e, nc)), np.zeros((n_e, nc), np.int32),
+                  np.full((n_e, nc), np.nan), np.zeros((n_e, nc), np.int32))
         ptrs = [None] * 4
+        extra = [None, None]
         if n_cols:
             ptrs = [arrays[0].ctypes.data_as(C.POINTER(C.c_int32)),
                     arrays[1].ctypes.data_as(C.POINTER(C.c_double)),
                     arrays[2].ctypes.data_as(C.POINTER(C.c_double)),
                     arrays[3].ctypes.data_as(C.POINTER(C.c_int32))]
-        d = _abi.negf_diag(*ptrs, 0, 0, 0.0, int(time_matvec), 0.0, 0, 0.0)
+            extra = [arrays[4].ctypes.data_as(C.POINTER(C.c_double)) if optical else None,
+                     arrays[5].ctypes.data_as(C.POINTER(C.c_int32))]
+        d = _abi.negf_diag(*ptrs, 0, 0, 0.0, int(time_matvec), 0.0, 0, 0.0, *extra)
     st = _lib().negf_transmission(op.handle, C.byref(o), n_e, _ptr(energies), _ptr(T),
                                   C.byref(d) if d is not None else None)
     if check:
@@ -192,6 +199,8 @@ def negf_transmission(op: Operator, energies, n_cols: Optional[int] = None, chec
                        int(d.n_not_converged), float(d.seconds), int(st))
     diag.extra.update(matvec_seconds=float(d.matvec_seconds),
                       matvec_launches=int(d.matvec_launches), matvec_bytes=float(d.matvec_bytes))
+    diag.refine_steps = arrays[5]
+    diag.optical_err = arrays[4] if optical else None
     return T, diag
 
 

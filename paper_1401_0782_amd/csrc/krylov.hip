@@ -22,6 +22,16 @@ namespace {
 
 constexpr int kT = 256;
 
+// The bilinear form r^T r of a nonzero complex vector can vanish (an
+// isotropic vector, such as e_1 + i e_2).  COCG then breaks down: beta_k =
+// rho_{k+1} / rho_k loses every digit.  A form below this fraction of
+// ||r||^2, which is rounding level in FP64, counts as a breakdown.
+constexpr double kIsotropic = 1e-15;
+
+__device__ inline bool isotropic(double2 rho, double nn) {
+    return nn > 0.0 && cabs2(rho) <= kIsotropic * kIsotropic * nn * nn;
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -262,7 +272,7 @@ __device__ void ms_bookkeeping(int c, double rr_x, double rr_y, double nn, IterS
         sh_sc[0] = a;
         sh_sc[1] = ck;
         sh_sc[2] = make_double2(sk / snew, skm1 / snew);
-        sh_sc[3] = make_double2(snew, cfinite(beta) ? 1.0 : 0.0);
+        sh_sc[3] = make_double2(snew, (cfinite(beta) && !isotropic(rho_new, nn)) ? 1.0 : 0.0);
         sh_sc[4] = beta;
         sh_sc[5] = make_double2(pre.s0 / sk, 0.0);
         st.rho[c] = rho_new;
@@ -314,11 +324,11 @@ __device__ void ms_bookkeeping(int c, double rr_x, double rr_y, double nn, IterS
     __syncthreads();
     if (threadIdx.x == 0) {
         st.k[c] = k + 1;
-        if (sh_sc[3].y == 0.0) {
-            // rho_{k+1} / rho_k not finite: r^T r vanished
-            st.done[c] = (sh_sc[3].x == 0.0) ? 1 + NEGF_ITEM_CONVERGED : 1 + NEGF_ITEM_BREAKDOWN;
-        } else if (sh_all) {
+        if (sh_all) {
             st.done[c] = 1 + NEGF_ITEM_CONVERGED;
+        } else if (sh_sc[3].y == 0.0) {
+            // r^T r vanished (rho_{k+1} / rho_k lost): converged if r itself did
+            st.done[c] = (sh_sc[3].x == 0.0) ? 1 + NEGF_ITEM_CONVERGED : 1 + NEGF_ITEM_BREAKDOWN;
         } else if (k + 1 >= st.max_iter) {
             st.done[c] = 1 + NEGF_ITEM_MAX_ITER;
         }
@@ -361,7 +371,8 @@ __global__ __launch_bounds__(kT) void k_update_ms(
     const double* __restrict__ e_kb, int n_proj, const int* __restrict__ kb_slot,
     const int* __restrict__ pt_off, const int* __restrict__ pt_proj,
     const double* __restrict__ pt_val, double2* __restrict__ ring, int ring_len, int w,
-    int64_t row0, int n_rows, double2* __restrict__ part_rr, double* __restrict__ part_nn) {
+    int64_t row0, int n_rows, int64_t row1, int n_rows1, double2* __restrict__ part_rr,
+    double* __restrict__ part_nn) {
     __shared__ double lds[3 * kT / 64];
     __shared__ double2 sh_alpha;
     __shared__ int sh_flag;
@@ -458,8 +469,11 @@ __global__ __launch_bounds__(kT) void k_update_ms(
             v.y -= ax * qn[u].y + ay * qn[u].x;
             rc[i] = v;
             if (dst) {
-                const int64_t ir = i - row0;
-                if (ir >= 0 && ir < n_rows) dst[ir] = to_d2<R>(v);
+                // kept rows: [row0, row0 + n0) then [row1, row1 + n_rows1)
+                const int n0 = n_rows - n_rows1;
+                const int64_t ir = i - row0, ir1 = i - row1;
+                if (ir >= 0 && ir < n0) dst[ir] = to_d2<R>(v);
+                else if (ir1 >= 0 && ir1 < n_rows1) dst[n0 + ir1] = to_d2<R>(v);
             }
             const double rx = v.x, ry = v.y;
             s[0] += rx * rx - ry * ry;
@@ -516,7 +530,7 @@ __global__ __launch_bounds__(kT) void k_reduce_beta_single(const double2* __rest
         st.k[c] = k + 1;
         if (snew <= inner_tol * st.bnorm[c]) {
             st.done[c] = 1 + NEGF_ITEM_CONVERGED;
-        } else if (!cfinite(beta)) {
+        } else if (!cfinite(beta) || isotropic(rho_new, s[2])) {
             st.done[c] = 1 + NEGF_ITEM_BREAKDOWN;
         } else if (k + 1 >= st.max_iter) {
             st.done[c] = 1 + NEGF_ITEM_MAX_ITER;
@@ -528,7 +542,8 @@ __global__ __launch_bounds__(kT) void k_reduce_beta_single(const double2* __rest
 template <typename R>
 __global__ __launch_bounds__(kT) void k_store_rows(const cplx_t<R>* __restrict__ r, int64_t N,
                                                    const int* __restrict__ rows, int64_t row0,
-                                                   int n_rows, double2* __restrict__ ring,
+                                                   int n_rows, int64_t row1, int n_rows1,
+                                                   double2* __restrict__ ring,
                                                    int ring_len, int w,
                                                    const int* __restrict__ done,
                                                    const int* __restrict__ kit, int slot_offset,
@@ -538,8 +553,9 @@ __global__ __launch_bounds__(kT) void k_store_rows(const cplx_t<R>* __restrict__
     const int slot = (kit[c] + slot_offset) % ring_len;
     double2* dst = ring + ((int64_t)slot * w + c) * n_rows;
     const cplx_t<R>* rc = r + (int64_t)c * N;
+    const int n0 = n_rows - n_rows1;
     for (int i = blockIdx.x * kT + threadIdx.x; i < n_rows; i += gridDim.x * kT) {
-        const int64_t gi = rows ? (int64_t)rows[i] : row0 + i;
+        const int64_t gi = rows ? (int64_t)rows[i] : (i < n0 ? row0 + i : row1 + (i - n0));
         dst[i] = to_d2<R>(rc[gi]);
     }
 }
@@ -636,11 +652,13 @@ void launch_reduce_beta_single(const double2* part_rr, const double* part_nn, in
 template <typename R>
 void launch_store_rows(const cplx_t<R>* r, int64_t N, int w, const int* rows, int64_t row0,
                        int n_rows, double2* ring, int ring_len, const IterState& st,
-                       int slot_offset, hipStream_t s, const int* only) {
+                       int slot_offset, hipStream_t s, const int* only, int64_t row1,
+                       int n_rows1) {
     int gx = (n_rows + kT - 1) / kT;
     if (gx > 256) gx = 256;
     dim3 g(gx, w);
-    hipLaunchKernelGGL((k_store_rows<R>), g, dim3(kT), 0, s, r, N, rows, row0, n_rows, ring,
+    hipLaunchKernelGGL((k_store_rows<R>), g, dim3(kT), 0, s, r, N, rows, row0, n_rows, row1,
+                       n_rows1, ring,
                        ring_len, w, st.done, st.k, slot_offset, only);
 }
 
@@ -656,7 +674,7 @@ void launch_store_rows(const cplx_t<R>* r, int64_t N, int w, const int* rows, in
                                       int64_t, const IterState&, const int*, hipStream_t);       \
     template void launch_store_rows<R>(const cplx_t<R>*, int64_t, int, const int*, int64_t, int, \
                                        double2*, int, const IterState&, int, hipStream_t,        \
-                                       const int*);
+                                       const int*, int64_t, int);
 INST(double)
 INST(float)
 #undef INST
@@ -733,7 +751,11 @@ __global__ __launch_bounds__(kT) void k_reduce_init(const double2* __restrict__ 
         st.beta[c] = make_double2(0.0, 0.0);
         st.alpha[c] = make_double2(0.0, 0.0);
         st.k[c] = 0;
-        st.done[c] = sk ? 1 + NEGF_ITEM_CONVERGED : ((n == 0.0) ? 1 + NEGF_ITEM_CONVERGED : 0);
+        // an isotropic start (b^T b = 0 with b != 0) cannot start COCG
+        st.done[c] = sk ? 1 + NEGF_ITEM_CONVERGED
+                        : ((n == 0.0) ? 1 + NEGF_ITEM_CONVERGED
+                                      : (isotropic(make_double2(s[0], s[1]), s[2])
+                                             ? 1 + NEGF_ITEM_BREAKDOWN : 0));
         if (st.qmr) {
             double* qs = st.qmr + 8 * c;
             qs[0] = n;  // tau_0 = ||r_0||
@@ -911,16 +933,16 @@ template <typename R>
 void launch_update_ms(cplx_t<R>* r, const cplx_t<R>* q, int64_t N, const IterState& st,
                       const double2* part_f, int nblk_f, const negf_op* op, const double2* kbc,
                       double2* ring, int ring_len, int64_t row0, int n_rows, double2* part_rr,
-                      double* part_nn, hipStream_t s) {
+                      double* part_nn, hipStream_t s, int64_t row1, int n_rows1) {
     dim3 g(part_blocks(N), st.w);
     const DeviceKB& kb = op->kb;
     const bool has_kb = kb.n_proj > 0;
     hipLaunchKernelGGL((k_update_ms<R>), g, dim3(kT), 0, s, r, q, N, st, part_f, nblk_f,
                        has_kb ? kbc : nullptr, kb.e, kb.n_proj, has_kb ? kb.slot : nullptr,
-                       kb.pt_off, kb.pt_proj, kb.pt_val, ring, ring_len, st.w, row0, n_rows, part_rr,
-                       part_nn);
+                       kb.pt_off, kb.pt_proj, kb.pt_val, ring, ring_len, st.w, row0, n_rows, row1,
+                       n_rows1, part_rr, part_nn);
 }
 template void launch_update_ms<double>(double2*, const double2*, int64_t, const IterState&,
                                        const double2*, int, const negf_op*, const double2*,
                                        double2*, int, int64_t, int, double2*, double*,
-                                       hipStream_t);
+                                       hipStream_t, int64_t, int);

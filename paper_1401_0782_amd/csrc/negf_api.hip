@@ -10,6 +10,7 @@
 #include <chrono>
 #include <atomic>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <string>
@@ -696,6 +697,13 @@ struct MSOut {
     int* h_status = nullptr;    // [n_src] column status
     double* h_resid = nullptr;  // [n_src][ng] residual estimate per energy
     int* h_shift_iters = nullptr; // [n_src][ng] iteration at which each energy converged (0: not)
+    // optical-theorem check (transmission mode): the kept rows go on past the
+    // n_rows - n_rows1 rows at row0 with the n_rows1 rows of the source side's
+    // absorbing region at row1; d_row_wo [n_rows] weights W on both ranges
+    int64_t row1 = 0;
+    int n_rows1 = 0;
+    const double* d_row_wo = nullptr;
+    double* h_optical = nullptr; // [n_src][ng] |sum W |g|^2 + Im g_jj| / |Im g_jj|
 };
 
 // iterations per blocked shift update (and per ring half).  X and P move once
@@ -715,293 +723,445 @@ static int shift_chunk(const negf_op* op) { return op->N >= 131072 ? 256 : 128; 
 // next queued column, so the block stays full until the queue runs dry and
 // only the last columns leave slots idle.  Each column's arithmetic is the
 // same as in a block of its own.
-static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, int n_src,
-                                        const int* cols, const double2* d_rhs,
-                                        const double* energies, int ng, const int* d_rows,
-                                        int64_t row0, int n_rows, const double* d_row_w,
-                                        const double* h_col_w, const MSOut& out,
-                                        int64_t* total_iters, hipStream_t s, MatvecTimer* tm) {
-    const int64_t N = op->N;
-    const int nblk = part_blocks(N);
+//
+// The run is resumable: start() queues the set-up, issue_chunk() queues one
+// chunk of iterations with its shift accumulation and the read-back of the
+// column flags, and after_chunk() does the host bookkeeping once that chunk
+// has finished (chunk_done() polls it without blocking).  One host thread
+// can so keep the streams of many runs busy (the junction batch).
+class MultiShiftRun {
+  public:
+    MultiShiftRun(negf_op* op, const Defaults& d, int w, int n_src, const int* cols,
+                  const double2* d_rhs, const double* energies, int ng, const int* d_rows,
+                  int64_t row0, int n_rows, const double* d_row_w, const double* h_col_w,
+                  const MSOut& out, int64_t* total_iters, hipStream_t s, MatvecTimer* tm)
+        : op_(op), d_(d), w_(w), n_src_(n_src), cols_(cols), d_rhs_(d_rhs), energies_(energies),
+          ng_(ng), d_rows_(d_rows), row0_(row0), n_rows_(n_rows), d_row_w_(d_row_w),
+          h_col_w_(h_col_w), out_(out), total_iters_(total_iters), s_(s), tm_(tm) {}
+    MultiShiftRun(const MultiShiftRun&) = delete;
+    MultiShiftRun& operator=(const MultiShiftRun&) = delete;
+    ~MultiShiftRun() {
+        // queued work may still use the events, the graph and the pinned
+        // flags: drain both streams first (the graph member is released after
+        // this body)
+        if (s_) (void)hipStreamSynchronize(s_);
+        if (side_) (void)hipStreamSynchronize(side_);
+        if (ev_coef_) (void)hipEventDestroy(ev_coef_);
+        if (ev_gemm_) (void)hipEventDestroy(ev_gemm_);
+        if (ev_chunk_) (void)hipEventDestroy(ev_chunk_);
+        if (h_flags_) {
+            std::lock_guard<std::mutex> lock(g_device_mu);
+            (void)hipHostFree(h_flags_);
+        }
+    }
+
+    negf_status start();
+    negf_status issue_chunk();
+    // true once the last issued chunk has finished (or its stream failed)
+    bool chunk_done() const { return hipEventQuery(ev_chunk_) != hipErrorNotReady; }
+    // host bookkeeping after a chunk; *busy = false once every column is done
+    negf_status after_chunk(bool* busy);
+    negf_status finish();
+
+  private:
+    negf_op* op_;
+    Defaults d_;
+    int w_, n_src_;
+    const int* cols_;
+    const double2* d_rhs_;
+    const double* energies_;
+    int ng_;
+    const int* d_rows_;
+    int64_t row0_;
+    int n_rows_;
+    const double* d_row_w_;
+    const double* h_col_w_;
+    MSOut out_;
+    int64_t* total_iters_;
+    hipStream_t s_;
+    MatvecTimer* tm_;
+
+    int64_t N_ = 0;
+    int nblk_ = 0, ch_ = 0, ring_len_ = 0;
+    double2 *r_ = nullptr, *p_ = nullptr, *p2_ = nullptr, *q_ = nullptr, *part_ = nullptr;
+    double2 *kbc_ = nullptr, *ring_ = nullptr, *X_ = nullptr, *P_ = nullptr, *part_f_ = nullptr;
+    double *part_nn_ = nullptr, *shift_ = nullptr;
+    int* d_cols_ = nullptr;
+    double2 *cx_ = nullptr, *cp_ = nullptr, *xi_a_ = nullptr, *carry_ = nullptr;
+    int *active_ = nullptr, *act_list_ = nullptr, *act_n_ = nullptr;
+    int* kstart_buf_[2] = {nullptr, nullptr};
+    int *clen_ = nullptr, *d_mask_ = nullptr, *d_notmask_ = nullptr;
+    hipStream_t side_ = nullptr;
+    hipEvent_t ev_coef_ = nullptr, ev_gemm_ = nullptr, ev_chunk_ = nullptr;
+    bool gemm_pending_ = false;
+    IterState st_;
+    bool fused_update_ = false;
+    double *tcol_ = nullptr, *col_w_ = nullptr, *d_opt_ = nullptr;
+    int* d_jloc_ = nullptr;
+    std::vector<int> h_jloc_;
+    std::vector<double> h_opt_;
+    int* h_flags_ = nullptr;  // pinned: done [w], then k [w]
+    std::vector<int> slot_src_, h_colsel_, h_mask_, h_notmask_, h_kprev_, h_si_;
+    std::vector<double> h_t_, h_res_, h_colw_;
+    int next_src_ = 0;
+    int launches_ = 0;
+    int steps_ = 0;
+    int running_ = 0;
+    ChunkGraph cg_;
+    bool use_graph_ = true;
+};
+
+negf_status MultiShiftRun::start() {
+    negf_op* op = op_;
+    const int w = w_, ng = ng_, n_rows = n_rows_;
+    hipStream_t s = s_;
+    N_ = op->N;
+    const int64_t N = N_;
+    nblk_ = part_blocks(N);
     // the stencil's z-chunking follows the number of running columns (finer
     // chunks keep the CUs busy when few columns remain); partials are sized for
     // the finest
     const int nblk_f_max = fused_partials(op, 1);
     // ring of 2c + 1 slots: while the GEMM of chunk j reads its c residuals,
     // chunk j + 1 stores the next c + 1 without touching them
-    const int ch = shift_chunk(op), ring_len = 2 * ch + 1;
-    if (n_src < w || (n_src > w && (!cols || out.d_out))) {
+    ch_ = shift_chunk(op);
+    ring_len_ = 2 * ch_ + 1;
+    if (n_src_ < w || (n_src_ > w && (!cols_ || out_.d_out))) {
         set_error("internal: column streaming needs unit right-hand sides in transmission mode");
         return NEGF_E_INVALID_ARG;
     }
-    double2 *r, *p, *p2, *q, *part, *kbc, *ring, *X, *P, *coef, *part_f;
-    double *part_nn, *shift;
-    int* d_cols;
-    CHK(ws(op, WS_R, (size_t)w * N, &r));
-    CHK(ws(op, WS_P, (size_t)w * N, &p));
-    CHK(ws(op, WS_Q, (size_t)w * N, &q));
-    CHK(ws(op, WS_X, (size_t)w * N, &p2));
-    CHK(ws(op, WS_PART, (size_t)w * nblk, &part));
-    CHK(ws(op, WS_PART2, (size_t)w * nblk, &part_nn));
-    CHK(ws(op, WS_PART3, (size_t)w * nblk_f_max, &part_f));
-    CHK(ws(op, WS_KBC, (size_t)w * std::max(1, op->kb.n_proj), &kbc));
-    CHK(ws(op, WS_SHIFT, (size_t)w, &shift));
-    CHK(ws(op, WS_COLJ, (size_t)w, &d_cols));
+    CHK(ws(op, WS_R, (size_t)w * N, &r_));
+    CHK(ws(op, WS_P, (size_t)w * N, &p_));
+    CHK(ws(op, WS_Q, (size_t)w * N, &q_));
+    CHK(ws(op, WS_X, (size_t)w * N, &p2_));
+    CHK(ws(op, WS_PART, (size_t)w * nblk_, &part_));
+    CHK(ws(op, WS_PART2, (size_t)w * nblk_, &part_nn_));
+    CHK(ws(op, WS_PART3, (size_t)w * nblk_f_max, &part_f_));
+    CHK(ws(op, WS_KBC, (size_t)w * std::max(1, op->kb.n_proj), &kbc_));
+    CHK(ws(op, WS_SHIFT, (size_t)w, &shift_));
+    CHK(ws(op, WS_COLJ, (size_t)w, &d_cols_));
     CHK(ws_get(op, WS_SINK, (size_t)w * op->nx * op->ny * sizeof(double2), &op->d_sink));
-    CHK(ws(op, WS_RING, (size_t)ring_len * w * n_rows, &ring));
-    CHK(ws(op, WS_XS, (size_t)w * ng * n_rows, &X));
-    CHK(ws(op, WS_PS, (size_t)w * ng * n_rows, &P));
+    CHK(ws(op, WS_RING, (size_t)ring_len_ * w * n_rows, &ring_));
+    CHK(ws(op, WS_XS, (size_t)w * ng * n_rows, &X_));
+    CHK(ws(op, WS_PS, (size_t)w * ng * n_rows, &P_));
     // coefficients: CX, CP [w][ch][ng]; xi_a [w][ng][2]; carry [w][ng];
     // ints: active [w][ng], act_list [w][ng], act_n [w]
-    const size_t n_cxp = (size_t)w * ch * ng;
+    const size_t n_cxp = (size_t)w * ch_ * ng;
+    double2* coef = nullptr;
     CHK(ws(op, WS_COEF, 2 * n_cxp + 3 * (size_t)w * ng + ((size_t)w * ng + w + 1) / 2 + 1, &coef));
-    double2* cx = coef;
-    double2* cp = coef + n_cxp;
-    double2* xi_a = coef + 2 * n_cxp;
-    double2* carry = xi_a + 2 * (size_t)w * ng;
-    int* active = (int*)(carry + (size_t)w * ng);
-    int* act_list = active + (size_t)w * ng;
-    int* act_n = act_list + (size_t)w * ng;
+    cx_ = coef;
+    cp_ = coef + n_cxp;
+    xi_a_ = coef + 2 * n_cxp;
+    carry_ = xi_a_ + 2 * (size_t)w * ng;
+    active_ = (int*)(carry_ + (size_t)w * ng);
+    act_list_ = active_ + (size_t)w * ng;
+    act_n_ = act_list_ + (size_t)w * ng;
     // per slot: iteration count at the chunk start (two chunks' worth: the GEMM
     // of one chunk overlaps the next), chunk length, slot masks
-    int* slots;
+    int* slots = nullptr;
     CHK(ws(op, WS_SLOTS, 5 * (size_t)w, &slots));
-    int* kstart_buf[2] = {slots, slots + w};
-    int* clen = slots + 2 * w;
-    int* d_mask = slots + 3 * w;
-    int* d_notmask = slots + 4 * w;
+    kstart_buf_[0] = slots;
+    kstart_buf_[1] = slots + w;
+    clen_ = slots + 2 * w;
+    d_mask_ = slots + 3 * w;
+    d_notmask_ = slots + 4 * w;
+    {
+        std::lock_guard<std::mutex> lock(g_device_mu);
+        HIPCHK(hipHostMalloc((void**)&h_flags_, 2 * (size_t)w * sizeof(int), hipHostMallocDefault));
+    }
     // the GEMM of chunk j runs on the side stream while chunk j + 1 iterates;
     // ev_coef orders it after its coefficients, ev_gemm orders later users of
-    // X, P and the coefficient buffers after it
-    hipStream_t side = op->side_stream;
-    hipEvent_t ev_coef = nullptr, ev_gemm = nullptr;
-    HIPCHK(hipEventCreateWithFlags(&ev_coef, hipEventDisableTiming));
-    if (hipEventCreateWithFlags(&ev_gemm, hipEventDisableTiming) != hipSuccess) {
-        (void)hipEventDestroy(ev_coef);
-        HIPCHK(hipErrorOutOfMemory);
-    }
-    struct EventGuard {
-        hipEvent_t a, b;
-        ~EventGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
-    } ev_guard{ev_coef, ev_gemm};
-    bool gemm_pending = false;
-    IterState st;
-    CHK(make_state(op, w, ng, d.max_iter, d.tol, true, &st, ch));
+    // X, P and the coefficient buffers after it; ev_chunk marks the end of the
+    // chunk's read-back of the column flags
+    side_ = op->side_stream;
+    HIPCHK(hipEventCreateWithFlags(&ev_coef_, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev_gemm_, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev_chunk_, hipEventDisableTiming));
+    CHK(make_state(op, w, ng, d_.max_iter, d_.tol, true, &st_, ch_));
     // fused update (alpha, projector term, r, kept rows) needs contiguous kept rows
-    const bool fused_update = (d_rows == nullptr) && !fused_update_disabled();
+    fused_update_ = (d_rows_ == nullptr) && !fused_update_disabled();
 
     // seed: the highest energy of the group (usually the slowest system)
-    double e_seed = energies[0];
-    for (int g = 0; g < ng; ++g) e_seed = std::max(e_seed, energies[g]);
+    double e_seed = energies_[0];
+    for (int g = 0; g < ng; ++g) e_seed = std::max(e_seed, energies_[g]);
     std::vector<double> h_shift(w, e_seed), h_delta((size_t)w * ng);
     for (int c = 0; c < w; ++c)
-        for (int g = 0; g < ng; ++g) h_delta[(size_t)c * ng + g] = energies[g] - e_seed;
-    HIPCHK(hipMemcpyAsync(shift, h_shift.data(), w * sizeof(double), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(st.deltas, h_delta.data(), h_delta.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        for (int g = 0; g < ng; ++g) h_delta[(size_t)c * ng + g] = energies_[g] - e_seed;
+    HIPCHK(hipMemcpyAsync(shift_, h_shift.data(), w * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(st_.deltas, h_delta.data(), h_delta.size() * sizeof(double), hipMemcpyHostToDevice, s));
 
     // slot -> source column (-1: idle); the first w columns start together
-    std::vector<int> slot_src(w), h_colsel(w, 0), h_mask(w), h_notmask(w);
-    for (int c = 0; c < w; ++c) slot_src[c] = c;
-    int next_src = w;
-    if (cols) {
-        for (int c = 0; c < w; ++c) h_colsel[c] = cols[c];
-        HIPCHK(hipMemcpyAsync(d_cols, h_colsel.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
-        launch_init_unit<double>(r, nullptr, N, w, d_cols, s);
+    slot_src_.assign(w, 0);
+    h_colsel_.assign(w, 0);
+    h_mask_.assign(w, 0);
+    h_notmask_.assign(w, 0);
+    for (int c = 0; c < w; ++c) slot_src_[c] = c;
+    next_src_ = w;
+    if (cols_) {
+        for (int c = 0; c < w; ++c) h_colsel_[c] = cols_[c];
+        HIPCHK(hipMemcpyAsync(d_cols_, h_colsel_.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
+        launch_init_unit<double>(r_, nullptr, N, w, d_cols_, s);
     } else {
-        HIPCHK(hipMemcpyAsync(r, d_rhs, (size_t)w * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(r_, d_rhs_, (size_t)w * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
     }
-    HIPCHK(hipMemsetAsync(X, 0, (size_t)w * ng * n_rows * sizeof(double2), s));
-    HIPCHK(hipMemsetAsync(P, 0, (size_t)w * ng * n_rows * sizeof(double2), s));
-    HIPCHK(hipMemsetAsync(carry, 0, (size_t)w * ng * sizeof(double2), s));
-    launch_norms<double>(r, N, w, nullptr, part, part_nn, s);
-    launch_reduce_init(part, part_nn, nblk, st, nullptr, s);
-    launch_store_rows<double>(r, N, w, d_rows, row0, n_rows, ring, ring_len, st, 0, s);
+    HIPCHK(hipMemsetAsync(X_, 0, (size_t)w * ng * n_rows * sizeof(double2), s));
+    HIPCHK(hipMemsetAsync(P_, 0, (size_t)w * ng * n_rows * sizeof(double2), s));
+    HIPCHK(hipMemsetAsync(carry_, 0, (size_t)w * ng * sizeof(double2), s));
+    launch_norms<double>(r_, N, w, nullptr, part_, part_nn_, s);
+    launch_reduce_init(part_, part_nn_, nblk_, st_, nullptr, s);
+    launch_store_rows<double>(r_, N, w, d_rows_, row0_, n_rows, ring_, ring_len_, st_, 0, s,
+                              nullptr, out_.row1, out_.n_rows1);
     HIPCHK(hipGetLastError());
 
     // per-slot readbacks and the T scratch of finishing slots
-    double *tcol = nullptr, *col_w = nullptr;
-    if (out.h_tcol) {
-        CHK(ws(op, WS_TCOL, (size_t)w * ng + w, &tcol));
-        col_w = tcol + (size_t)w * ng;
+    if (out_.h_tcol || out_.h_optical) {
+        // t [w][ng], column weights [w], optical errors [w][ng], source rows [w]
+        CHK(ws(op, WS_TCOL, 2 * (size_t)w * ng + 2 * (size_t)w, &tcol_));
+        col_w_ = tcol_ + (size_t)w * ng;
+        d_opt_ = col_w_ + w;
+        d_jloc_ = reinterpret_cast<int*>(d_opt_ + (size_t)w * ng);
+        h_jloc_.assign(w, 0);
     }
-    std::vector<int> h_done(w), h_k(w), h_kprev(w, 0), h_si;
-    std::vector<double> h_t, h_res;
-    std::vector<double> h_colw(w, 0.0);
-    int launches = 0;
-    ChunkGraph cg;
-    DrainGuard drain{s, side};
-    const bool use_graph = graphs_enabled();
-    int running = w;  // columns still iterating at the chunk start
-    while (true) {
-        // a streaming block runs whole chunks (each column stops at its own
-        // max_iter); a single block stops at max_iter
-        const int steps = (n_src > w) ? ch : std::min(ch, d.max_iter - launches);
-        // the z-chunking for the running columns; the graph holds the full-width
-        // shape, narrower chunks run eagerly
-        const int w_geom = std::max(1, running);
-        const int nblk_f = fused_partials(op, w_geom);
-        int* kstart = kstart_buf[(launches / ch) & 1];
-        // timing: every period-th chunk runs eagerly with its stencil launches
-        // bracketed by events, the others replay as graphs; the GEMM overlaps
-        // timed and untimed chunks alike, so that the timed launches share the
-        // device as all the others do
-        const int chunk_index = launches / ch;
-        tm->active = tm->on && chunk_index % tm->period == 0;
-        hipStream_t gemm_stream = side;
-        HIPCHK(hipMemcpyAsync(kstart, st.k, w * sizeof(int), hipMemcpyDeviceToDevice, s));
-        auto issue = [&]() -> negf_status {
-            for (int it = 0; it < steps; ++it) {
-                // p ping-pongs so that halo reads of the fused kernel see p_{k-1};
-                // every column starts at an even k
-                double2* pin = (it & 1) ? p2 : p;
-                double2* pout = (it & 1) ? p : p2;
-                hipEvent_t e0, e1;
-                CHK(tm->next(&e0, &e1));
-                launch_cocg_apply<double>(op, r, pin, pout, q, w, shift, st.done, st.k, st.beta,
-                                          part_f, kbc, s, e0, e1, !fused_update, w_geom);
-                if (fused_update) {
-                    // alpha, projector term, r update and kept rows in one launch
-                    launch_update_ms<double>(r, q, N, st, part_f, nblk_f, op, kbc, ring, ring_len,
-                                             row0, n_rows, part, part_nn, s);
-                    launch_reduce_beta_multishift(part, part_nn, nblk, st, s);
-                    continue;
-                }
-                launch_reduce_alpha(part_f, nblk_f, st, s, op->kb.n_proj ? kbc : nullptr,
-                                    op->kb.e, op->kb.n_proj);
-                launch_r_update<double>(r, q, nullptr, nullptr, part, part_nn, st, N, s);
-                launch_store_rows<double>(r, N, w, d_rows, row0, n_rows, ring, ring_len, st, 1, s);
-                launch_reduce_beta_multishift(part, part_nn, nblk, st, s);
-            }
-            return NEGF_OK;
-        };
-        CHK(run_chunk(cg, use_graph && steps == ch && w_geom == w, s, tm, issue));
-        // fold the chunk's iterations into X and P of every energy: the
-        // coefficients here (after the previous GEMM has read its own), the GEMM
-        // on the side stream, overlapping the next chunk
-        if (gemm_pending) HIPCHK(hipStreamWaitEvent(s, ev_gemm, 0));
-        launch_chunk_coef(st, kstart, clen, cx, cp, xi_a, carry, active, act_list, act_n, s);
-        HIPCHK(hipEventRecord(ev_coef, s));
-        HIPCHK(hipStreamWaitEvent(gemm_stream, ev_coef, 0));
-        launch_gemm_xp(ring, ring_len, w, n_rows, kstart, clen, st, cx, cp, xi_a, active, act_list,
-                       act_n, X, P, gemm_stream);
-        HIPCHK(hipEventRecord(ev_gemm, gemm_stream));
-        gemm_pending = true;
-        HIPCHK(hipGetLastError());
-        launches += steps;
-        HIPCHK(hipMemcpyAsync(h_done.data(), st.done, w * sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(h_k.data(), st.k, w * sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        CHK(tm->flush());
-        if (tm->active) {
-            // algorithmic bytes of the timed launches: per column-iteration r and
-            // p_{k-1} in, p_k and q out; V once per launch
-            int64_t ci = 0;
-            for (int c = 0; c < w; ++c) ci += h_k[c] - h_kprev[c];
-            tm->bytes += 4.0 * sizeof(double2) * (double)N * (double)ci + 8.0 * N * steps;
-        }
-        h_kprev = h_k;
-        const bool stop = (n_src == w) && launches >= d.max_iter;
-        // slots whose column is done hand over its results
-        int n_fin = 0;
-        for (int c = 0; c < w; ++c) {
-            h_mask[c] = (slot_src[c] >= 0 && (h_done[c] != 0 || stop)) ? 1 : 0;
-            n_fin += h_mask[c];
-        }
-        // finished slots read X and restarted ones clear it: the GEMM first
-        if (n_fin > 0) HIPCHK(hipStreamWaitEvent(s, ev_gemm, 0));
-        if (n_fin > 0 && out.d_out) {
-            // column mode: X stays in place and is copied out at the end
-            for (int c = 0; c < w; ++c)
-                if (h_mask[c]) slot_src[c] = -1;
-        } else if (n_fin > 0) {
-            const bool all_fin = (n_fin == w);
-            HIPCHK(hipMemcpyAsync(d_mask, h_mask.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
-            if (out.h_tcol) {
-                for (int c = 0; c < w; ++c) h_colw[c] = h_mask[c] ? h_col_w[slot_src[c]] : 0.0;
-                HIPCHK(hipMemcpyAsync(col_w, h_colw.data(), w * sizeof(double), hipMemcpyHostToDevice, s));
-                launch_t_from_x(X, n_rows, w, ng, d_row_w, col_w, all_fin ? nullptr : d_mask, tcol, s);
-                h_t.resize((size_t)w * ng);
-                HIPCHK(hipMemcpyAsync(h_t.data(), tcol, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
-            }
-            h_res.resize((size_t)w * ng);
-            h_si.resize((size_t)w * ng);
-            HIPCHK(hipMemcpyAsync(h_res.data(), st.sres, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipMemcpyAsync(h_si.data(), st.sconv, (size_t)w * ng * sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            for (int c = 0; c < w; ++c) {
-                if (!h_mask[c]) continue;
-                const int j = slot_src[c];
-                *total_iters += h_k[c];
-                if (out.h_iters) out.h_iters[j] = h_k[c];
-                if (out.h_status) out.h_status[j] = h_done[c] ? h_done[c] - 1 : NEGF_ITEM_MAX_ITER;
-                for (int g = 0; g < ng; ++g) {
-                    const size_t so = (size_t)c * ng + g, dof = (size_t)j * ng + g;
-                    if (out.h_tcol) out.h_tcol[dof] = h_t[so];
-                    if (out.h_resid) out.h_resid[dof] = h_res[so];
-                    if (out.h_shift_iters) out.h_shift_iters[dof] = h_si[so];
-                }
-                slot_src[c] = -1;
-            }
-        }
-        // restart finished slots on queued columns
-        int n_new = 0;
-        for (int c = 0; c < w; ++c) {
-            h_mask[c] = 0;
-            if (slot_src[c] < 0 && next_src < n_src && n_src > w) {
-                slot_src[c] = next_src++;
-                h_colsel[c] = cols[slot_src[c]];
-                h_mask[c] = 1;
-                ++n_new;
-            }
-            h_notmask[c] = 1 - h_mask[c];
-        }
-        if (n_new > 0) {
-            HIPCHK(hipStreamWaitEvent(s, ev_gemm, 0));  // X, P, carry are rewritten below
-            HIPCHK(hipMemcpyAsync(d_mask, h_mask.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(d_notmask, h_notmask.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(d_cols, h_colsel.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
-            launch_init_unit<double>(r, nullptr, N, w, d_cols, s, d_mask);
-            for (int c = 0; c < w; ++c)
-                if (h_mask[c]) h_kprev[c] = 0;
-            for (int c = 0; c < w; ++c) {
-                if (!h_mask[c]) continue;
-                const size_t xo = (size_t)c * ng * n_rows;
-                HIPCHK(hipMemsetAsync(X + xo, 0, (size_t)ng * n_rows * sizeof(double2), s));
-                HIPCHK(hipMemsetAsync(P + xo, 0, (size_t)ng * n_rows * sizeof(double2), s));
-                HIPCHK(hipMemsetAsync(carry + (size_t)c * ng, 0, (size_t)ng * sizeof(double2), s));
-            }
-            launch_norms<double>(r, N, w, d_notmask, part, part_nn, s);
-            launch_reduce_init(part, part_nn, nblk, st, nullptr, s, d_mask);
-            launch_store_rows<double>(r, N, w, d_rows, row0, n_rows, ring, ring_len, st, 0, s, d_mask);
-            HIPCHK(hipGetLastError());
-        }
-        bool busy = false;
-        running = 0;
-        for (int c = 0; c < w; ++c) {
-            busy = busy || slot_src[c] >= 0;
-            // restarted slots run; live ones run unless their column is done
-            running += (slot_src[c] >= 0 && (h_mask[c] || h_done[c] == 0)) ? 1 : 0;
-        }
-        if (!busy) break;
+    if (out_.h_optical && (!cols_ || out_.n_rows1 < 1 || !out_.d_row_wo)) {
+        set_error("internal: the optical check needs unit sources and their own absorbing rows");
+        return NEGF_E_INVALID_ARG;
     }
+    h_kprev_.assign(w, 0);
+    h_colw_.assign(w, 0.0);
+    launches_ = 0;
+    use_graph_ = graphs_enabled();
+    running_ = w;  // columns still iterating at the chunk start
+    return NEGF_OK;
+}
 
-    if (gemm_pending) HIPCHK(hipStreamWaitEvent(s, ev_gemm, 0));
-    if (out.d_out) {
-        // column mode: every slot is still live here (n_src == w)
-        for (int c = 0; c < w; ++c) {
-            *total_iters += h_k[c];
-            if (out.h_iters) out.h_iters[c] = h_k[c];
-            if (out.h_status) out.h_status[c] = h_done[c] ? h_done[c] - 1 : NEGF_ITEM_MAX_ITER;
+negf_status MultiShiftRun::issue_chunk() {
+    negf_op* op = op_;
+    const int w = w_;
+    const int64_t N = N_;
+    hipStream_t s = s_;
+    const int ch = ch_;
+    MatvecTimer* tm = tm_;
+    // a streaming block runs whole chunks (each column stops at its own
+    // max_iter); a single block stops at max_iter
+    steps_ = (n_src_ > w) ? ch : std::min(ch, d_.max_iter - launches_);
+    const int steps = steps_;
+    // the z-chunking for the running columns; the graph holds the full-width
+    // shape, narrower chunks run eagerly
+    const int w_geom = std::max(1, running_);
+    const int nblk_f = fused_partials(op, w_geom);
+    int* kstart = kstart_buf_[(launches_ / ch) & 1];
+    // timing: every period-th chunk runs eagerly with its stencil launches
+    // bracketed by events, the others replay as graphs; the GEMM overlaps
+    // timed and untimed chunks alike, so that the timed launches share the
+    // device as all the others do
+    const int chunk_index = launches_ / ch;
+    tm->active = tm->on && chunk_index % tm->period == 0;
+    hipStream_t gemm_stream = side_;
+    HIPCHK(hipMemcpyAsync(kstart, st_.k, w * sizeof(int), hipMemcpyDeviceToDevice, s));
+    auto issue = [&]() -> negf_status {
+        for (int it = 0; it < steps; ++it) {
+            // p ping-pongs so that halo reads of the fused kernel see p_{k-1};
+            // every column starts at an even k
+            double2* pin = (it & 1) ? p2_ : p_;
+            double2* pout = (it & 1) ? p_ : p2_;
+            hipEvent_t e0, e1;
+            CHK(tm->next(&e0, &e1));
+            launch_cocg_apply<double>(op, r_, pin, pout, q_, w, shift_, st_.done, st_.k, st_.beta,
+                                      part_f_, kbc_, s, e0, e1, !fused_update_, w_geom);
+            if (fused_update_) {
+                // alpha, projector term, r update and kept rows in one launch
+                launch_update_ms<double>(r_, q_, N, st_, part_f_, nblk_f, op, kbc_, ring_,
+                                         ring_len_, row0_, n_rows_, part_, part_nn_, s,
+                                         out_.row1, out_.n_rows1);
+                launch_reduce_beta_multishift(part_, part_nn_, nblk_, st_, s);
+                continue;
+            }
+            launch_reduce_alpha(part_f_, nblk_f, st_, s, op->kb.n_proj ? kbc_ : nullptr,
+                                op->kb.e, op->kb.n_proj);
+            launch_r_update<double>(r_, q_, nullptr, nullptr, part_, part_nn_, st_, N, s);
+            launch_store_rows<double>(r_, N, w, d_rows_, row0_, n_rows_, ring_, ring_len_, st_, 1, s,
+                                      nullptr, out_.row1, out_.n_rows1);
+            launch_reduce_beta_multishift(part_, part_nn_, nblk_, st_, s);
         }
-        launch_copy_out(X, n_rows, w, ng, out.d_out, out.out_col_stride, out.out_shift_stride, s);
-        if (out.h_resid)
-            HIPCHK(hipMemcpyAsync(out.h_resid, st.sres, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
-        if (out.h_shift_iters)
-            HIPCHK(hipMemcpyAsync(out.h_shift_iters, st.sconv, (size_t)w * ng * sizeof(int), hipMemcpyDeviceToHost, s));
+        return NEGF_OK;
+    };
+    CHK(run_chunk(cg_, use_graph_ && steps == ch && w_geom == w, s, tm, issue));
+    // fold the chunk's iterations into X and P of every energy: the
+    // coefficients here (after the previous GEMM has read its own), the GEMM
+    // on the side stream, overlapping the next chunk
+    if (gemm_pending_) HIPCHK(hipStreamWaitEvent(s, ev_gemm_, 0));
+    launch_chunk_coef(st_, kstart, clen_, cx_, cp_, xi_a_, carry_, active_, act_list_, act_n_, s);
+    HIPCHK(hipEventRecord(ev_coef_, s));
+    HIPCHK(hipStreamWaitEvent(gemm_stream, ev_coef_, 0));
+    launch_gemm_xp(ring_, ring_len_, w, n_rows_, kstart, clen_, st_, cx_, cp_, xi_a_, active_,
+                   act_list_, act_n_, X_, P_, gemm_stream);
+    HIPCHK(hipEventRecord(ev_gemm_, gemm_stream));
+    gemm_pending_ = true;
+    HIPCHK(hipGetLastError());
+    launches_ += steps;
+    HIPCHK(hipMemcpyAsync(h_flags_, st_.done, w * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h_flags_ + w, st_.k, w * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(ev_chunk_, s));
+    return NEGF_OK;
+}
+
+negf_status MultiShiftRun::after_chunk(bool* busy) {
+    negf_op* op = op_;
+    const int w = w_, ng = ng_, n_rows = n_rows_;
+    const int64_t N = N_;
+    hipStream_t s = s_;
+    MatvecTimer* tm = tm_;
+    HIPCHK(hipEventSynchronize(ev_chunk_));
+    const int* h_done = h_flags_;
+    const int* h_k = h_flags_ + w;
+    CHK(tm->flush());
+    if (tm->active) {
+        // algorithmic bytes of the timed launches: per column-iteration r and
+        // p_{k-1} in, p_k and q out; V once per launch
+        int64_t ci = 0;
+        for (int c = 0; c < w; ++c) ci += h_k[c] - h_kprev_[c];
+        tm->bytes += 4.0 * sizeof(double2) * (double)N * (double)ci + 8.0 * N * steps_;
+    }
+    for (int c = 0; c < w; ++c) h_kprev_[c] = h_k[c];
+    const bool stop = (n_src_ == w) && launches_ >= d_.max_iter;
+    // slots whose column is done hand over its results
+    int n_fin = 0;
+    for (int c = 0; c < w; ++c) {
+        h_mask_[c] = (slot_src_[c] >= 0 && (h_done[c] != 0 || stop)) ? 1 : 0;
+        n_fin += h_mask_[c];
+    }
+    // finished slots read X and restarted ones clear it: the GEMM first
+    if (n_fin > 0) HIPCHK(hipStreamWaitEvent(s, ev_gemm_, 0));
+    if (n_fin > 0 && out_.d_out) {
+        // column mode: X stays in place and is copied out at the end
+        for (int c = 0; c < w; ++c)
+            if (h_mask_[c]) slot_src_[c] = -1;
+    } else if (n_fin > 0) {
+        const bool all_fin = (n_fin == w);
+        HIPCHK(hipMemcpyAsync(d_mask_, h_mask_.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
+        if (out_.h_tcol) {
+            for (int c = 0; c < w; ++c) h_colw_[c] = h_mask_[c] ? h_col_w_[slot_src_[c]] : 0.0;
+            HIPCHK(hipMemcpyAsync(col_w_, h_colw_.data(), w * sizeof(double), hipMemcpyHostToDevice, s));
+            launch_t_from_x(X_, n_rows, w, ng, d_row_w_, col_w_, all_fin ? nullptr : d_mask_, tcol_, s);
+            h_t_.resize((size_t)w * ng);
+            HIPCHK(hipMemcpyAsync(h_t_.data(), tcol_, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        if (out_.h_optical) {
+            // local kept-row index of each finishing slot's own source point
+            const int n0 = n_rows - out_.n_rows1;
+            for (int c = 0; c < w; ++c)
+                h_jloc_[c] = h_mask_[c] ? n0 + (int)(cols_[slot_src_[c]] - out_.row1) : 0;
+            HIPCHK(hipMemcpyAsync(d_jloc_, h_jloc_.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
+            launch_optical(X_, n_rows, n_rows, w, ng, out_.d_row_wo, d_jloc_,
+                           all_fin ? nullptr : d_mask_, d_opt_, s);
+            h_opt_.resize((size_t)w * ng);
+            HIPCHK(hipMemcpyAsync(h_opt_.data(), d_opt_, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        h_res_.resize((size_t)w * ng);
+        h_si_.resize((size_t)w * ng);
+        HIPCHK(hipMemcpyAsync(h_res_.data(), st_.sres, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h_si_.data(), st_.sconv, (size_t)w * ng * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int c = 0; c < w; ++c) {
+            if (!h_mask_[c]) continue;
+            const int j = slot_src_[c];
+            *total_iters_ += h_k[c];
+            if (out_.h_iters) out_.h_iters[j] = h_k[c];
+            if (out_.h_status) out_.h_status[j] = h_done[c] ? h_done[c] - 1 : NEGF_ITEM_MAX_ITER;
+            for (int g = 0; g < ng; ++g) {
+                const size_t so = (size_t)c * ng + g, dof = (size_t)j * ng + g;
+                if (out_.h_tcol) out_.h_tcol[dof] = h_t_[so];
+                if (out_.h_optical) out_.h_optical[dof] = h_opt_[so];
+                if (out_.h_resid) out_.h_resid[dof] = h_res_[so];
+                if (out_.h_shift_iters) out_.h_shift_iters[dof] = h_si_[so];
+            }
+            slot_src_[c] = -1;
+        }
+    }
+    // restart finished slots on queued columns
+    int n_new = 0;
+    for (int c = 0; c < w; ++c) {
+        h_mask_[c] = 0;
+        if (slot_src_[c] < 0 && next_src_ < n_src_ && n_src_ > w) {
+            slot_src_[c] = next_src_++;
+            h_colsel_[c] = cols_[slot_src_[c]];
+            h_mask_[c] = 1;
+            ++n_new;
+        }
+        h_notmask_[c] = 1 - h_mask_[c];
+    }
+    if (n_new > 0) {
+        HIPCHK(hipStreamWaitEvent(s, ev_gemm_, 0));  // X, P, carry are rewritten below
+        HIPCHK(hipMemcpyAsync(d_mask_, h_mask_.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_notmask_, h_notmask_.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_cols_, h_colsel_.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
+        launch_init_unit<double>(r_, nullptr, N, w, d_cols_, s, d_mask_);
+        for (int c = 0; c < w; ++c)
+            if (h_mask_[c]) h_kprev_[c] = 0;
+        for (int c = 0; c < w; ++c) {
+            if (!h_mask_[c]) continue;
+            const size_t xo = (size_t)c * ng * n_rows;
+            HIPCHK(hipMemsetAsync(X_ + xo, 0, (size_t)ng * n_rows * sizeof(double2), s));
+            HIPCHK(hipMemsetAsync(P_ + xo, 0, (size_t)ng * n_rows * sizeof(double2), s));
+            HIPCHK(hipMemsetAsync(carry_ + (size_t)c * ng, 0, (size_t)ng * sizeof(double2), s));
+        }
+        launch_norms<double>(r_, N, w, d_notmask_, part_, part_nn_, s);
+        launch_reduce_init(part_, part_nn_, nblk_, st_, nullptr, s, d_mask_);
+        launch_store_rows<double>(r_, N, w, d_rows_, row0_, n_rows, ring_, ring_len_, st_, 0, s,
+                                  d_mask_, out_.row1, out_.n_rows1);
+        HIPCHK(hipGetLastError());
+    }
+    bool any = false;
+    running_ = 0;
+    for (int c = 0; c < w; ++c) {
+        any = any || slot_src_[c] >= 0;
+        // restarted slots run; live ones run unless their column is done
+        running_ += (slot_src_[c] >= 0 && (h_mask_[c] || h_done[c] == 0)) ? 1 : 0;
+    }
+    (void)op;
+    *busy = any;
+    return NEGF_OK;
+}
+
+negf_status MultiShiftRun::finish() {
+    const int w = w_, ng = ng_, n_rows = n_rows_;
+    hipStream_t s = s_;
+    if (gemm_pending_) HIPCHK(hipStreamWaitEvent(s, ev_gemm_, 0));
+    if (out_.d_out) {
+        // column mode: every slot is still live here (n_src == w)
+        const int* h_done = h_flags_;
+        const int* h_k = h_flags_ + w;
+        for (int c = 0; c < w; ++c) {
+            *total_iters_ += h_k[c];
+            if (out_.h_iters) out_.h_iters[c] = h_k[c];
+            if (out_.h_status) out_.h_status[c] = h_done[c] ? h_done[c] - 1 : NEGF_ITEM_MAX_ITER;
+        }
+        launch_copy_out(X_, n_rows, w, ng, out_.d_out, out_.out_col_stride, out_.out_shift_stride, s);
+        if (out_.h_resid)
+            HIPCHK(hipMemcpyAsync(out_.h_resid, st_.sres, (size_t)w * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (out_.h_shift_iters)
+            HIPCHK(hipMemcpyAsync(out_.h_shift_iters, st_.sconv, (size_t)w * ng * sizeof(int), hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     return NEGF_OK;
+}
+
+static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, int n_src,
+                                        const int* cols, const double2* d_rhs,
+                                        const double* energies, int ng, const int* d_rows,
+                                        int64_t row0, int n_rows, const double* d_row_w,
+                                        const double* h_col_w, const MSOut& out,
+                                        int64_t* total_iters, hipStream_t s, MatvecTimer* tm) {
+    MultiShiftRun run(op, d, w, n_src, cols, d_rhs, energies, ng, d_rows, row0, n_rows, d_row_w,
+                      h_col_w, out, total_iters, s, tm);
+    CHK(run.start());
+    bool busy = true;
+    while (busy) {
+        CHK(run.issue_chunk());
+        CHK(run.after_chunk(&busy));
+    }
+    return run.finish();
 }
 
 // launchers of adjoint.hip
@@ -1081,6 +1241,9 @@ static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, c
     HIPCHK(hipMemcpyAsync(bn64, nu, w * sizeof(double), hipMemcpyDeviceToDevice, s));
 
     std::vector<int> h_done(w), h_odone(w), h_k(w), iters(w, 0), refine(w, 0);
+    // items whose inner COCG broke down stop refining once the outer residual
+    // shows they did not converge anyway
+    std::vector<int> broke(w, 0), final_break(w, 0);
     int outer = 0;
     ChunkGraph cg;
     DrainGuard drain{s, nullptr};
@@ -1094,6 +1257,15 @@ static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, c
         }
         HIPCHK(hipMemcpyAsync(h_odone.data(), odone, w * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        bool forced = false;
+        for (int c = 0; c < w; ++c)
+            if (broke[c] && !h_odone[c]) {
+                h_odone[c] = 1;
+                final_break[c] = 1;
+                forced = true;
+            }
+        if (forced)
+            HIPCHK(hipMemcpyAsync(odone, h_odone.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
         bool all = true;
         for (int c = 0; c < w; ++c) all = all && h_odone[c];
         if (all || outer >= d.max_refine) break;
@@ -1136,7 +1308,10 @@ static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, c
             if (alld || k_host >= d.max_iter) break;
         }
         HIPCHK(hipMemcpyAsync(h_k.data(), st.k, w * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h_done.data(), st.done, w * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        for (int c = 0; c < w; ++c)
+            if (!h_odone[c] && h_done[c] == 1 + NEGF_ITEM_BREAKDOWN) broke[c] = 1;
         int64_t col_iters = 0;
         for (int c = 0; c < w; ++c)
             if (!h_odone[c]) {
@@ -1152,7 +1327,9 @@ static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, c
     for (int c = 0; c < w; ++c) {
         *total_iters += iters[c];
         if (out.h_iters) out.h_iters[c] = iters[c];
-        if (out.h_status) out.h_status[c] = h_odone[c] ? NEGF_ITEM_CONVERGED : NEGF_ITEM_MAX_ITER;
+        if (out.h_status)
+            out.h_status[c] = final_break[c] ? NEGF_ITEM_BREAKDOWN
+                                             : (h_odone[c] ? NEGF_ITEM_CONVERGED : NEGF_ITEM_MAX_ITER);
         if (out.h_refine) out.h_refine[c] = refine[c];
     }
     if (out.h_resid)
@@ -1232,6 +1409,15 @@ static int pick_core(const Defaults& d) {
     return d.precision == NEGF_FP64 ? NEGF_CORE_MULTISHIFT : NEGF_CORE_PER_ENERGY;
 }
 
+// Status of one energy of a multi-shift column: converged when its residual
+// estimate met tol (energies freeze as they converge, so those that froze
+// before a breakdown of the column keep their results), else the column's
+// breakdown, else out of iterations
+static int ms_item_status(double resid, int col_status, double tol) {
+    if (resid <= tol * 1.0000001) return NEGF_ITEM_CONVERGED;
+    return col_status == NEGF_ITEM_BREAKDOWN ? NEGF_ITEM_BREAKDOWN : NEGF_ITEM_MAX_ITER;
+}
+
 static negf_status final_status(int n_bad, int n_break) {
     if (n_break > 0) {
         set_error("%d items broke down", n_break);
@@ -1270,13 +1456,36 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
     make_sides(op, d.direction, &sd);
     CHK(restrict_sides(d, &sd));
     const int n_cols = (int)sd.cols.size();
+    const bool want_opt = diag && diag->optical_err;
+    const int64_t plane = (int64_t)op->nx * op->ny;
+    // the optical check keeps the source side's absorbing rows as well: T
+    // weights W_dst on the destination rows and 0 on those, the check's
+    // weights W on both
+    const bool rl = d.direction == NEGF_DIR_RL;
+    const int64_t row1 = (rl ? op->zr0 : op->zl0) * plane;
+    const int n_rows1 = (want_opt && core == NEGF_CORE_MULTISHIFT)
+                            ? (int)(((rl ? op->zr1 : op->zl1) - (rl ? op->zr0 : op->zl0)) * plane)
+                            : 0;
+    const int n_keep = sd.n_rows + n_rows1;
+    std::vector<double> roww(sd.roww), row_wo;
+    if (n_rows1) {
+        roww.resize(n_keep, 0.0);
+        row_wo = sd.roww;
+        const std::vector<double>& wsrc = rl ? op->cap_r : op->cap_l;
+        for (int r = 0; r < n_rows1; ++r) row_wo.push_back(wsrc[(row1 + r) / plane]);
+    }
     double* d_roww = nullptr;
-    CHK(ws(op, WS_ROWW, (size_t)sd.n_rows, &d_roww));
-    HIPCHK(hipMemcpyAsync(d_roww, sd.roww.data(), sd.n_rows * sizeof(double), hipMemcpyHostToDevice, s));
+    CHK(ws(op, WS_ROWW, (size_t)n_keep * (n_rows1 ? 2 : 1), &d_roww));
+    HIPCHK(hipMemcpyAsync(d_roww, roww.data(), n_keep * sizeof(double), hipMemcpyHostToDevice, s));
+    double* d_row_wo = n_rows1 ? d_roww + n_keep : nullptr;
+    if (n_rows1)
+        HIPCHK(hipMemcpyAsync(d_row_wo, row_wo.data(), n_keep * sizeof(double), hipMemcpyHostToDevice, s));
     // tcol[e][c]
     std::vector<double> tcol((size_t)n_e * n_cols, 0.0);
     std::vector<int> iters((size_t)n_e * n_cols, 0), status((size_t)n_e * n_cols, 0);
     std::vector<double> resid((size_t)n_e * n_cols, 0.0);
+    std::vector<double> optical(want_opt ? (size_t)n_e * n_cols : 0, 0.0);
+    std::vector<int> refine((size_t)n_e * n_cols, 0);
     int64_t total_iters = 0;
     if (core == NEGF_CORE_MULTISHIFT) {
         const int ng_max = d.shift_group ? std::min(d.shift_group, n_e) : n_e;
@@ -1284,7 +1493,7 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
         // the shard's columns stream through one block of slots; with
         // NEGF_NO_COLUMN_STREAM=1 each block of wmax columns runs on its own
         const bool stream = !column_stream_disabled();
-        std::vector<double> blk_t, blk_r;
+        std::vector<double> blk_t, blk_r, blk_o;
         std::vector<int> blk_it, blk_st, blk_si;
         for (int g0 = 0; g0 < n_e; g0 += ng_max) {
             const int ng = std::min(ng_max, n_e - g0);
@@ -1297,26 +1506,33 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
                 blk_it.assign(n_src, 0);
                 blk_st.assign(n_src, 0);
                 blk_si.assign((size_t)n_src * ng, 0);
+                blk_o.assign(want_opt ? (size_t)n_src * ng : 0, 0.0);
                 MSOut mo;
                 mo.h_tcol = blk_t.data();
                 mo.h_iters = blk_it.data();
                 mo.h_status = blk_st.data();
                 mo.h_resid = blk_r.data();
                 mo.h_shift_iters = blk_si.data();
+                if (want_opt) {
+                    mo.row1 = row1;
+                    mo.n_rows1 = n_rows1;
+                    mo.d_row_wo = d_row_wo;
+                    mo.h_optical = blk_o.data();
+                }
                 CHK(run_multishift_block(op, d, w, n_src, sd.cols.data() + c0, nullptr, energies + g0,
-                                         ng, nullptr, sd.row0, sd.n_rows, d_roww,
+                                         ng, nullptr, sd.row0, n_keep, d_roww,
                                          sd.colw.data() + c0, mo, &total_iters, s, &tm));
                 for (int c = 0; c < n_src; ++c)
                     for (int g = 0; g < ng; ++g) {
                         const size_t o = (size_t)(g0 + g) * n_cols + c0 + c;
                         tcol[o] = blk_t[(size_t)c * ng + g];
                         resid[o] = blk_r[(size_t)c * ng + g];
+                        if (want_opt) optical[o] = blk_o[(size_t)c * ng + g];
                         // iterations this energy needed (the column's count if it never froze)
                         iters[o] = blk_si[(size_t)c * ng + g] ? blk_si[(size_t)c * ng + g] : blk_it[c];
                         // a column that hit max_iter can still have converged
                         // energies; judge each by its own residual estimate
-                        status[o] = (blk_st[c] == NEGF_ITEM_BREAKDOWN) ? NEGF_ITEM_BREAKDOWN
-                                    : (resid[o] <= d.tol * 1.0000001 ? NEGF_ITEM_CONVERGED : NEGF_ITEM_MAX_ITER);
+                        status[o] = ms_item_status(resid[o], blk_st[c], d.tol);
                     }
             }
         }
@@ -1329,8 +1545,25 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
         std::vector<double> b_res, b_t;
         double* d_colw = nullptr;
         double* d_t = nullptr;
-        CHK(ws(op, WS_TCOL, (size_t)2 * wmax, &d_colw));
+        // column weights [w], t [w], optical errors [w], source points [w]
+        CHK(ws(op, WS_TCOL, (size_t)4 * wmax, &d_colw));
         d_t = d_colw + wmax;
+        double* d_opt = d_t + wmax;
+        int* d_jg = reinterpret_cast<int*>(d_opt + wmax);
+        double* d_wfull = nullptr;  // W_L + W_R per grid point, for the optical check
+        if (want_opt) {
+            std::vector<double> wf((size_t)op->N);
+            for (int64_t i = 0; i < op->N; ++i) {
+                const int z = (int)(i / plane);
+                wf[i] = op->cap_l[z] + op->cap_r[z];
+            }
+            CHK(ws(op, WS_GAMMA, (size_t)op->N, &d_wfull));
+            HIPCHK(hipMemcpyAsync(d_wfull, wf.data(), wf.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        std::vector<double> b_o;
+        std::vector<int> b_rf;
         for (int64_t i0 = 0; i0 < n_items; i0 += wmax) {
             const int w = (int)std::min<int64_t>(wmax, n_items - i0);
             icol.resize(w); ie.resize(w); colw.resize(w);
@@ -1342,15 +1575,22 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
                 colw[c] = sd.colw[j];
             }
             b_it.assign(w, 0); b_st.assign(w, 0); b_res.assign(w, 0.0); b_t.assign(w, 0.0);
+            b_o.assign(w, 0.0); b_rf.assign(w, 0);
             PEOut po;
             po.h_iters = b_it.data();
             po.h_status = b_st.data();
             po.h_resid = b_res.data();
+            po.h_refine = b_rf.data();
             CHK(run_per_energy(op, d, w, icol.data(), nullptr, ie.data(), po, &total_iters, s, &tm));
             double2* x64 = (double2*)op->bufs[WS_X64].ptr;
             HIPCHK(hipMemcpyAsync(d_colw, colw.data(), w * sizeof(double), hipMemcpyHostToDevice, s));
             launch_weighted_norm(x64, op->N, w, sd.row0, sd.n_rows, d_roww, d_colw, d_t, s);
             HIPCHK(hipMemcpyAsync(b_t.data(), d_t, w * sizeof(double), hipMemcpyDeviceToHost, s));
+            if (want_opt) {
+                HIPCHK(hipMemcpyAsync(d_jg, icol.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
+                launch_optical(x64, op->N, (int)op->N, w, 1, d_wfull, d_jg, nullptr, d_opt, s);
+                HIPCHK(hipMemcpyAsync(b_o.data(), d_opt, w * sizeof(double), hipMemcpyDeviceToHost, s));
+            }
             HIPCHK(hipStreamSynchronize(s));
             for (int c = 0; c < w; ++c) {
                 const size_t o = (size_t)(i0 + c);  // == e * n_cols + j
@@ -1358,6 +1598,8 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
                 iters[o] = b_it[c];
                 status[o] = b_st[c];
                 resid[o] = b_res[c];
+                refine[o] = b_rf[c];
+                if (want_opt) optical[o] = b_o[c];
             }
         }
     }
@@ -1378,6 +1620,8 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
         if (diag->resid) std::copy(resid.begin(), resid.end(), diag->resid);
         if (diag->t_col) std::copy(tcol.begin(), tcol.end(), diag->t_col);
         if (diag->item_status) std::copy(status.begin(), status.end(), diag->item_status);
+        if (diag->optical_err) std::copy(optical.begin(), optical.end(), diag->optical_err);
+        if (diag->refine_steps) std::copy(refine.begin(), refine.end(), diag->refine_steps);
         (void)n;
         diag->total_iters = total_iters;
         diag->n_not_converged = n_bad + n_break;
@@ -1489,9 +1733,7 @@ static negf_status solve_columns_impl(negf_op* op, const negf_opts* opts, int32_
                 for (int c = 0; c < w; ++c)
                     for (int g = 0; g < ng; ++g)
                         status[(size_t)(g0 + g) * n_rhs + c0 + c] =
-                            (blk_st[c] == NEGF_ITEM_BREAKDOWN) ? NEGF_ITEM_BREAKDOWN
-                            : (blk_r[(size_t)c * ng + g] <= d.tol * 1.0000001 ? NEGF_ITEM_CONVERGED
-                                                                              : NEGF_ITEM_MAX_ITER);
+                            ms_item_status(blk_r[(size_t)c * ng + g], blk_st[c], d.tol);
             }
         }
     } else {
@@ -1978,6 +2220,85 @@ extern "C" negf_status negf_set_launch_shape(negf_op* op, int32_t block_width, i
     return NEGF_OK;
 }
 
+// One junction of the batch in the multi-shift core: its source columns
+// stream through one block of slots (a single MultiShiftRun), which the
+// batch's host thread advances chunk by chunk.
+struct BatchJob {
+    int index = 0;
+    negf_op* op = nullptr;
+    Defaults d;
+    Sides sd;
+    int n_e = 0;
+    std::vector<double> blk_t, blk_r;
+    std::vector<int> blk_it, blk_st, blk_si;
+    int64_t total_iters = 0;
+    MatvecTimer tm;
+    std::unique_ptr<MultiShiftRun> run;
+};
+
+// Whether junction i of the batch runs as one resumable multi-shift run (FP64
+// multi-shift core, every energy in one shift group, streamed columns); the
+// others go through negf_transmission's own driver, one at a time.
+static bool batch_interleaves(const Defaults& d) {
+    return pick_core(d) == NEGF_CORE_MULTISHIFT && d.precision == NEGF_FP64 &&
+           d.shift_group == 0 && !column_stream_disabled();
+}
+
+static negf_status batch_job_start(BatchJob* job, const negf_opts* opts, const double* energies) {
+    negf_op* op = job->op;
+    CHK(read_opts(opts, &job->d));
+    CHK(check_energies(job->n_e, energies));
+    HIPCHK(hipSetDevice(op->device));
+    make_sides(op, job->d.direction, &job->sd);
+    CHK(restrict_sides(job->d, &job->sd));
+    const int n_cols = (int)job->sd.cols.size();
+    const int ng = job->n_e;
+    const int wmax = job->d.block_width ? job->d.block_width : (op->tuned_w ? op->tuned_w : 64);
+    const int w = std::min(wmax, n_cols);
+    hipStream_t s = op->own_stream;
+    double* d_roww = nullptr;
+    CHK(ws(op, WS_ROWW, (size_t)job->sd.n_rows, &d_roww));
+    HIPCHK(hipMemcpyAsync(d_roww, job->sd.roww.data(), job->sd.n_rows * sizeof(double),
+                          hipMemcpyHostToDevice, s));
+    job->blk_t.assign((size_t)n_cols * ng, 0.0);
+    job->blk_r.assign((size_t)n_cols * ng, 0.0);
+    job->blk_it.assign(n_cols, 0);
+    job->blk_st.assign(n_cols, 0);
+    job->blk_si.assign((size_t)n_cols * ng, 0);
+    MSOut mo;
+    mo.h_tcol = job->blk_t.data();
+    mo.h_iters = job->blk_it.data();
+    mo.h_status = job->blk_st.data();
+    mo.h_resid = job->blk_r.data();
+    mo.h_shift_iters = job->blk_si.data();
+    CHK(job->tm.init(0));
+    job->run = std::make_unique<MultiShiftRun>(op, job->d, w, n_cols, job->sd.cols.data(), nullptr,
+                                               energies, ng, nullptr, job->sd.row0, job->sd.n_rows,
+                                               d_roww, job->sd.colw.data(), mo, &job->total_iters,
+                                               s, &job->tm);
+    CHK(job->run->start());
+    return job->run->issue_chunk();
+}
+
+// T(E) of a finished job, reduced as negf_transmission reduces it
+static negf_status batch_job_result(BatchJob* job, double* T) {
+    const int n_cols = (int)job->sd.cols.size();
+    const int ng = job->n_e;
+    int n_bad = 0, n_break = 0;
+    for (int e = 0; e < ng; ++e) {
+        double acc = 0.0;
+        for (int c = 0; c < n_cols; ++c) {
+            const size_t o = (size_t)c * ng + e;
+            acc += job->blk_t[o];
+            const int st = ms_item_status(job->blk_r[o], job->blk_st[c], job->d.tol);
+            if (st == NEGF_ITEM_BREAKDOWN) ++n_break;
+            else if (st != NEGF_ITEM_CONVERGED) ++n_bad;
+        }
+        T[e] = acc;
+    }
+    return final_status(n_bad, n_break);
+}
+
 extern "C" negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* ops,
                                                const negf_opts* opts, const int32_t* n_e,
                                                const double* const* energies, double* const* T,
@@ -2012,54 +2333,109 @@ extern "C" negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* op
         cost[i] = (double)op->N * (double)(op->zr1 - op->zr0) * op->nx * op->ny * n_e[i];
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    const int n_workers = std::max(1, std::min(n_ops, max_concurrent > 0 ? max_concurrent : 4));
-    std::vector<negf_status> st(n_ops, NEGF_OK);
-    std::vector<std::string> msg(n_ops);
-    std::atomic<int> next{0};
+    const int n_slots = std::max(1, std::min(n_ops, max_concurrent > 0 ? max_concurrent : 4));
     int device = 0;
     HIPCHK(hipGetDevice(&device));
-    // Each worker hands one set of workspace buffers from junction to junction.
-    // Junctions run largest first, so later ones usually fit what an earlier one
-    // left: no device allocation or free in between, either of which would
-    // synchronise the device under the other workers' streams.
-    std::vector<std::vector<Buffer>> pools(n_workers, std::vector<Buffer>(WS_COUNT));
-    std::vector<std::vector<void*>> to_free(n_workers);
-    auto worker = [&](int k) {
-        (void)hipSetDevice(device);
-        std::vector<Buffer>& pool = pools[k];
-        while (true) {
-            const int t = next.fetch_add(1);
-            if (t >= n_ops) break;
-            const int i = order[t];
-            negf_op* op = ops[i];
-            for (int sl = 0; sl < WS_COUNT; ++sl)
-                if (!op->bufs[sl].ptr) std::swap(op->bufs[sl], pool[sl]);
-            st[i] = transmission_impl(op, opts, n_e[i], energies[i], T[i], nullptr);
-            if (st[i] != NEGF_OK) msg[i] = g_last_error;
-            (void)hipStreamSynchronize(op->own_stream);
-            (void)hipStreamSynchronize(op->side_stream);
-            // take the junction's buffers back (the larger one where both exist;
-            // the other is freed after the batch)
-            for (int sl = 0; sl < WS_COUNT; ++sl) {
-                Buffer& b = op->bufs[sl];
-                if (!b.ptr) continue;
-                if (pool[sl].ptr && pool[sl].bytes >= b.bytes) {
-                    to_free[k].push_back(b.ptr);
-                } else {
-                    if (pool[sl].ptr) to_free[k].push_back(pool[sl].ptr);
-                    pool[sl] = b;
-                }
-                b = Buffer{};
+    std::vector<negf_status> st(n_ops, NEGF_OK);
+    std::vector<std::string> msg(n_ops);
+    // One host thread keeps up to n_slots junctions in flight, each on its
+    // operator's own stream: it queues a junction's next chunk as soon as the
+    // previous one has finished (polled with event queries, no blocking wait
+    // on any one stream), so the device always holds the queued chunks of
+    // every slot.  Each slot hands one set of workspace buffers from junction
+    // to junction (largest first, so later ones usually fit what an earlier
+    // one left): no device allocation or free in between.
+    std::vector<std::vector<Buffer>> pools(n_slots, std::vector<Buffer>(WS_COUNT));
+    std::vector<void*> to_free;
+    std::vector<std::unique_ptr<BatchJob>> slot(n_slots);
+    size_t next = 0;
+    auto take_buffers = [&](int k, negf_op* op) {
+        for (int sl = 0; sl < WS_COUNT; ++sl)
+            if (!op->bufs[sl].ptr) std::swap(op->bufs[sl], pools[k][sl]);
+    };
+    auto return_buffers = [&](int k, negf_op* op) {
+        (void)hipStreamSynchronize(op->own_stream);
+        (void)hipStreamSynchronize(op->side_stream);
+        // keep the larger buffer of each kind; the other is freed after the batch
+        for (int sl = 0; sl < WS_COUNT; ++sl) {
+            Buffer& b = op->bufs[sl];
+            if (!b.ptr) continue;
+            if (pools[k][sl].ptr && pools[k][sl].bytes >= b.bytes) {
+                to_free.push_back(b.ptr);
+            } else {
+                if (pools[k][sl].ptr) to_free.push_back(pools[k][sl].ptr);
+                pools[k][sl] = b;
             }
-            op->d_sink = nullptr;
+            b = Buffer{};
+        }
+        op->d_sink = nullptr;
+    };
+    auto end_job = [&](int k, negf_status s_job) {
+        BatchJob* job = slot[k].get();
+        const int i = job->index;
+        if (s_job == NEGF_OK && job->run) s_job = job->run->finish();
+        job->run.reset();  // drains its streams
+        if (s_job == NEGF_OK) {
+            s_job = batch_job_result(job, T[i]);
+        }
+        st[i] = s_job;
+        if (s_job != NEGF_OK) msg[i] = g_last_error;
+        return_buffers(k, job->op);
+        slot[k].reset();
+    };
+    // starts the next junction in slot k; junctions that do not interleave
+    // run to completion here
+    auto fill = [&](int k) {
+        while (next < order.size()) {
+            const int i = order[next++];
+            negf_op* op = ops[i];
+            Defaults d;
+            const negf_status s_opt = read_opts(opts, &d);
+            take_buffers(k, op);
+            if (s_opt != NEGF_OK || !batch_interleaves(d)) {
+                st[i] = (s_opt != NEGF_OK) ? s_opt
+                                           : transmission_impl(op, opts, n_e[i], energies[i], T[i], nullptr);
+                if (st[i] != NEGF_OK) msg[i] = g_last_error;
+                return_buffers(k, op);
+                continue;
+            }
+            slot[k] = std::make_unique<BatchJob>();
+            BatchJob* job = slot[k].get();
+            job->index = i;
+            job->op = op;
+            job->n_e = n_e[i];
+            const negf_status s_start = batch_job_start(job, opts, energies[i]);
+            if (s_start != NEGF_OK) {
+                end_job(k, s_start);
+                continue;
+            }
+            return;
         }
     };
-    std::vector<std::thread> threads;
-    for (int k = 0; k < n_workers; ++k) threads.emplace_back(worker, k);
-    for (auto& th : threads) th.join();
+    for (int k = 0; k < n_slots; ++k) fill(k);
+    while (true) {
+        bool any = false, progressed = false;
+        for (int k = 0; k < n_slots; ++k) {
+            BatchJob* job = slot[k].get();
+            if (!job) continue;
+            any = true;
+            if (!job->run->chunk_done()) continue;
+            progressed = true;
+            (void)hipSetDevice(job->op->device);
+            bool busy = false;
+            negf_status s_job = job->run->after_chunk(&busy);
+            if (s_job == NEGF_OK && busy) s_job = job->run->issue_chunk();
+            if (s_job != NEGF_OK || !busy) {
+                end_job(k, s_job);
+                fill(k);
+            }
+        }
+        if (!any) break;
+        if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    (void)hipSetDevice(device);
     (void)hipDeviceSynchronize();
-    for (auto& v : to_free)
-        for (void* ptr : v) dev_free(ptr);
+    for (void* ptr : to_free) dev_free(ptr);
     for (auto& pool : pools)
         for (auto& b : pool) dev_free(b.ptr);
     negf_status first = NEGF_OK;

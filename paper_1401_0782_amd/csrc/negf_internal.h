@@ -196,11 +196,13 @@ void prepare_stencil_kernels(const negf_op* op);
 int fused_partials(const negf_op* op, int w);
 // multi-shift alpha + projector term + r update + kept-row store in one launch
 // (krylov.hip); ring == null skips the row store
+// kept rows: n_rows in all (the ring's row stride), [row0, row0 + n_rows -
+// n_rows1) followed by [row1, row1 + n_rows1)
 template <typename R>
 void launch_update_ms(cplx_t<R>* r, const cplx_t<R>* q, int64_t N, const IterState& st,
                       const double2* part_f, int nblk_f, const negf_op* op, const double2* kbc,
                       double2* ring, int ring_len, int64_t row0, int n_rows, double2* part_rr,
-                      double* part_nn, hipStream_t s);
+                      double* part_nn, hipStream_t s, int64_t row1 = 0, int n_rows1 = 0);
 // r -= alpha q; x += alpha p (COCG), or with st.qmr the pending smoothed step
 // d = a d + b p, x += d, where p is then the previous direction
 template <typename R>
@@ -220,7 +222,8 @@ void launch_reduce_beta_single(const double2* part_rr, const double* part_nn, in
 template <typename R>
 void launch_store_rows(const cplx_t<R>* r, int64_t N, int w, const int* rows, int64_t row0,
                        int n_rows, double2* ring, int ring_len, const IterState& st,
-                       int slot_offset, hipStream_t s, const int* only = nullptr);
+                       int slot_offset, hipStream_t s, const int* only = nullptr,
+                       int64_t row1 = 0, int n_rows1 = 0);
 // blocked multi-shift accumulation (shift.hip)
 // kstart[c]: the column's iteration count at the start of the chunk; the
 // coefficient kernel writes each column's chunk length to clen for the GEMM
@@ -236,5 +239,10 @@ void launch_gemm_xp(const double2* ring, int ring_len, int w, int n_rows, const 
                     const int* act_n, double2* X, double2* P, hipStream_t s);
 void launch_t_from_x(const double2* X, int n_rows, int w, int ng, const double* row_w,
                      const double* col_w, const int* only, double* t, hipStream_t s);
+// optical-theorem error per (column, energy) of iterates X[c][g][stride]:
+// |sum_i row_w[i] |x_i|^2 + Im x[jloc[c]]| / |Im x[jloc[c]]| over i < n_keep
+void launch_optical(const double2* X, int64_t stride, int n_keep, int w, int ng,
+                    const double* row_w, const int* jloc, const int* only, double* out,
+                    hipStream_t s);
 void launch_copy_out(const double2* X, int n_rows, int w, int ng, double2* out, int64_t col_stride,
                      int64_t shift_stride, hipStream_t s);

@@ -365,6 +365,34 @@ __global__ __launch_bounds__(kT) void k_t_from_x(const double2* __restrict__ X, 
     }
 }
 
+// The optical theorem of one column g_j = A(E)^-1 e_j: with A = E - H + iW and
+// H real symmetric, Im(g_j^H A g_j) gives sum_i W_i |g_ij|^2 = -Im g_jj, so
+// |sum_i W_i |g_ij|^2 + Im g_jj| / |Im g_jj| measures how well the iterate
+// solves its system.  One work-group per (energy, column).
+__global__ __launch_bounds__(kT) void k_optical(const double2* __restrict__ X, int64_t stride,
+                                                int n_keep, int ng,
+                                                const double* __restrict__ row_w,
+                                                const int* __restrict__ jloc,
+                                                const int* __restrict__ only,
+                                                double* __restrict__ out) {
+    __shared__ double lds[kT / 64];
+    const int g = blockIdx.x, c = blockIdx.y;
+    if (only && !only[c]) return;
+    const double2* x = X + ((int64_t)c * ng + g) * stride;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n_keep; i += kT) s += row_w[i] * cabs2(x[i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (threadIdx.x % 64 == 0) lds[threadIdx.x / 64] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int wv = 0; wv < kT / 64; ++wv) tot += lds[wv];
+        const double im = x[jloc[c]].y;
+        out[(int64_t)c * ng + g] = fabs(tot + im) / fabs(im);
+    }
+}
+
 // out[g * shift_stride + c * col_stride + row] = X[c][g][row]
 __global__ __launch_bounds__(kT) void k_copy_out(const double2* __restrict__ X, int n_rows, int ng,
                                                  double2* __restrict__ out, int64_t col_stride,
@@ -412,6 +440,13 @@ void launch_t_from_x(const double2* X, int n_rows, int w, int ng, const double* 
                      const double* col_w, const int* only, double* t, hipStream_t s) {
     hipLaunchKernelGGL(k_t_from_x, dim3(ng, w), dim3(kT), 0, s, X, n_rows, ng, row_w, col_w, only,
                        t);
+}
+
+void launch_optical(const double2* X, int64_t stride, int n_keep, int w, int ng,
+                    const double* row_w, const int* jloc, const int* only, double* out,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_optical, dim3(ng, w), dim3(kT), 0, s, X, stride, n_keep, ng, row_w, jloc,
+                       only, out);
 }
 
 void launch_copy_out(const double2* X, int n_rows, int w, int ng, double2* out, int64_t col_stride,

@@ -51,6 +51,28 @@ def test_batch_uneven_wire_junctions(gpu_lib):
         assert np.array_equal(T, P.negf_transmission(op, j.energies, **kw))
 
 
+def test_batch_unconverged_and_mixed_paths(gpu_lib):
+    """A batch whose junctions all stop at max_iter reports NOT_CONVERGED per
+    junction with the same T as single calls; mixed precision (the per-energy
+    core, run junction by junction inside the batch) equals single calls."""
+    import paper_1401_0782_amd as P
+    from paper_1401_0782_amd import _abi
+
+    js = _junctions()
+    ops = [P.operator_from_wire(j) for j in js]
+    es = [j.energies for j in js]
+    kw = dict(tol=1e-12, max_iter=6)
+    Tb, st = P.negf_transmission_batch(ops, es, max_concurrent=2, check=False, **kw)
+    assert np.all(st == _abi.NEGF_E_NOT_CONVERGED)
+    for j, op, T in zip(js, ops, Tb):
+        assert np.array_equal(T, P.negf_transmission(op, j.energies, check=False, **kw))
+    km = dict(tol=1e-10, precision=P.NEGF_MIXED)
+    Tm, st = P.negf_transmission_batch(ops[:3], es[:3], **km)
+    assert np.all(st == 0)
+    for j, op, T in zip(js[:3], ops[:3], Tm):
+        assert np.array_equal(T, P.negf_transmission(op, j.energies, **km))
+
+
 def test_batch_rejects_shared_operator(gpu_lib):
     import paper_1401_0782_amd as P
     from paper_1401_0782_amd import NegfError
