@@ -187,6 +187,25 @@ negf_status negf_build_operator(const negf_grid* g, int32_t stencil_radius,
 negf_status negf_apply_operator(negf_op* op, int32_t precision, int32_t n_vec,
                                 const double* shifts, const negf_c64* x, negf_c64* y);
 
+/* The FP64 operator apply of negf_apply_operator without any device
+ * allocation, for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation after
+ * start-up.  Its scratch data (the n_vec shifts and the n_vec x n_proj
+ * projector coefficients) lives in a fixed array of
+ * NEGF_NOALLOC_SCRATCH_BYTES per GPU that the library holds until the
+ * process ends: 256-byte-rounded 8 n_vec plus 16 n_vec max(1, n_proj) bytes
+ * must fit, else NEGF_E_INVALID_ARG (nothing is launched).  Calls that
+ * overlap on one GPU share that array and race: serialise them.
+ *   shifts   n_vec energies E_c, host or device (a host array is copied into
+ *            the scratch array on the stream; under graph capture pass a
+ *            device array)
+ *   x, y     [n_vec][N] device memory, not overlapping
+ *   stream   hipStream_t to queue the work on and return without waiting, or
+ *            NULL: the op's own stream, waited for before returning */
+#define NEGF_NOALLOC_SCRATCH_BYTES (1 << 20)
+negf_status negf_apply_operator_noalloc(negf_op* op, int32_t n_vec, const double* shifts,
+                                        const negf_c64* x, negf_c64* y, void* stream);
+
 /* Columns of G(E) (Eq. 3): out[e][r][k] = (A(E_e)^-1 b_r)[row_idx[k]].
  *   n_e, energies   host energies
  *   n_rhs           number of right-hand sides

@@ -26,6 +26,7 @@ NEGF_SOLVER_COCG, NEGF_SOLVER_QMR = 0, 1
 EXPORTS = (
     "negf_build_operator",
     "negf_apply_operator",
+    "negf_apply_operator_noalloc",
     "negf_solve_columns",
     "negf_transmission",
     "negf_transmission_batch",
@@ -98,6 +99,7 @@ def load(path: str | None = None):
     lib.negf_build_operator.argtypes = [C.POINTER(negf_grid), C.c_int32, vp, C.POINTER(negf_kb),
                                         vp, vp, C.POINTER(vp)]
     lib.negf_apply_operator.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp]
+    lib.negf_apply_operator_noalloc.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     lib.negf_solve_columns.argtypes = [vp, C.POINTER(negf_opts), C.c_int32, vp, C.c_int32, vp, vp,
                                        C.c_int32, vp, vp, vp]
     lib.negf_transmission.argtypes = [vp, C.POINTER(negf_opts), C.c_int32, vp, vp,
@@ -115,7 +117,8 @@ def load(path: str | None = None):
     lib.negf_destroy.restype = None
     lib.negf_last_error.restype = C.c_char_p
     lib.negf_version.restype = C.c_char_p
-    for name in ("negf_build_operator", "negf_apply_operator", "negf_solve_columns",
+    for name in ("negf_build_operator", "negf_apply_operator", "negf_apply_operator_noalloc",
+                 "negf_solve_columns",
                  "negf_transmission", "negf_transmission_grad", "negf_transmission_batch",
                  "negf_tune", "negf_set_launch_shape", "negf_current",
                  "negf_spectral_transmission"):
