@@ -251,13 +251,18 @@ def measure_rows(names):
                      form="core B FP64", seconds=t, solves_per_s=n * E.size / t)
             else:
                 wts = np.ones(E.size)
-                run = lambda k: P.negf_transmission_grad(op, E, wts, tol=TOL, col_begin=0,
-                                                         col_count=k)
-                run(2)
-                _, t = timed(lambda: run(32))
-                emit(row=name, workload=f"wire 24x24x96 R=4, 32 cols x {E.size} E",
-                     form="dT/dV: core A forward + adjoint solves", seconds=t,
-                     item_solves_per_s=2 * 32 * E.size / t)
+                run = lambda c0, k: P.negf_transmission_grad(op, E, wts, tol=TOL, col_begin=c0,
+                                                             col_count=k, block_width=k)
+                run(0, 2)
+                # four 8-column shards spread over the 12 source planes
+                shards = [int(c) for c in np.linspace(0, n - 8, 4)]
+                _, t = timed(lambda: [run(c0, 8) for c0 in shards])
+                cols = 8 * len(shards)
+                emit(row=name, workload=f"wire 24x24x96 R=4, {cols} cols (shards at {shards}) "
+                     f"x {E.size} E", form="dT/dV: forward columns from the multi-shift core, "
+                     "adjoint solves in the per-energy core", seconds=t,
+                     item_solves_per_s=2 * cols * E.size / t,
+                     projected_full_minutes=t * n / cols / 60.0)
         elif name == "large":
             w = make_wire(5)
             op = P.operator_from_wire(w)

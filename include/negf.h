@@ -296,12 +296,44 @@ negf_status negf_set_launch_shape(negf_op* op, int32_t block_width, int32_t wg_t
 /* Adjoint gradient of L = sum_e weights[e] T(E_e) with respect to the local
  * potential: dL_dV[r] = sum_e w_e 8 Re sum_{j in R} W_R,j lambda_j(r) g_j(r),
  * with g_j = A^-1 e_j and lambda_j = A^-1 (W_L o conj(g_j)) solved with the
- * same complex symmetric operator (A^T = A, Eq. 6).
+ * same complex symmetric operator (A^T = A, Eq. 6).  The forward columns g_j
+ * (right-hand sides independent of E) come from one multi-shift run per
+ * block of columns at every energy, all rows kept; the adjoint solves, whose
+ * right-hand sides depend on E, run in the per-energy core.  opts->tol bounds
+ * both (FP64; opts->precision is not used).
  *   weights   n_e host values; dL_dV  N host or device FP64;
  *   T         optional host n_e output of T(E) (nullable). */
 negf_status negf_transmission_grad(negf_op* op, const negf_opts* opts, int32_t n_e,
                                    const double* energies, const double* weights,
                                    double* dL_dV, double* T);
+
+/* Eigenpairs (eps_i, U_i) of the open-system operator H_op = H - i(W_L + W_R)
+ * (Eq. 8) whose real parts lie in [e_lo - margin, e_hi + margin], for the
+ * spectral route of negf_spectral_transmission (Sec. II.C; the paper obtains
+ * them with ARPACK's iterative complex diagonalisation).  Complex-symmetric
+ * Lanczos in the bilinear form u^T v on the device, every new vector
+ * re-orthogonalised twice against all earlier ones (this keeps the process
+ * from duplicating or missing eigenpairs, the instability Sec. II.D reports
+ * for plain complex-symmetric Lanczos); the eigenvalues of the tridiagonal
+ * projection by implicit QL with complex orthogonal rotations, its
+ * eigenvectors by inverse iteration, the Ritz vectors V y on the device.
+ * The low end of the spectrum, where transport windows lie, converges first.
+ *   n_lanczos   Krylov dimension K (at most N; K = N finds every eigenpair
+ *               of small operators); device memory (K + 1) N complex FP64
+ *   resid_tol   a Ritz pair is returned only if
+ *               ||H_op U - eps U|| / ||U|| <= resid_tol (Ha)
+ *   max_pairs   capacity of eps, U and resid
+ *   eps         host [max_pairs] out, ascending real part
+ *   U           [max_pairs][N] out (host or device), U_i^T U_i = 1 (Eqs. 9-11)
+ *   resid       host [max_pairs] out (nullable): each pair's residual
+ *   n_found     host out: pairs returned
+ * NEGF_E_BREAKDOWN if no start vector has a nonzero bilinear form or the
+ * tridiagonal eigenvalue iteration breaks down; a Krylov space that closes
+ * early (an invariant subspace, or a new vector with w^T w = 0) ends the
+ * process there and returns what it found. */
+negf_status negf_eigenpairs(negf_op* op, double e_lo, double e_hi, double margin,
+                            int32_t n_lanczos, double resid_tol, int32_t max_pairs,
+                            negf_c64* eps, negf_c64* U, double* resid, int32_t* n_found);
 
 /* Landauer current of Eq. 1 from a transmission curve, on the device:
  *   I(V_b) = (1/pi) int T(E) [f(E - mu_L) - f(E - mu_R)] dE   (atomic units,

@@ -21,6 +21,7 @@ from .api import (  # noqa: F401
     negf_apply_operator,
     negf_build_operator,
     negf_current,
+    negf_eigenpairs,
     negf_solve_columns,
     negf_spectral_transmission,
     negf_transmission,

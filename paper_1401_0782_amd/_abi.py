@@ -34,6 +34,7 @@ EXPORTS = (
     "negf_set_launch_shape",
     "negf_current",
     "negf_spectral_transmission",
+    "negf_eigenpairs",
     "negf_transmission_grad",
     "negf_destroy",
     "negf_last_error",
@@ -113,6 +114,8 @@ def load(path: str | None = None):
     lib.negf_spectral_transmission.argtypes = [vp, C.c_int32, vp, vp, C.c_double, C.c_int32, vp,
                                                vp]
     lib.negf_current.argtypes = [C.c_int32, vp, vp, C.c_int32, vp, C.c_double, C.c_double, vp, vp]
+    lib.negf_eigenpairs.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_double,
+                                    C.c_int32, vp, vp, vp, vp]
     lib.negf_destroy.argtypes = [vp]
     lib.negf_destroy.restype = None
     lib.negf_last_error.restype = C.c_char_p
@@ -121,7 +124,7 @@ def load(path: str | None = None):
                  "negf_solve_columns",
                  "negf_transmission", "negf_transmission_grad", "negf_transmission_batch",
                  "negf_tune", "negf_set_launch_shape", "negf_current",
-                 "negf_spectral_transmission"):
+                 "negf_spectral_transmission", "negf_eigenpairs"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

@@ -283,6 +283,26 @@ def negf_spectral_transmission(op: Operator, eps, U, energies, keep: float = 1.0
     return T
 
 
+def negf_eigenpairs(op: Operator, e_lo: float, e_hi: float, margin: float = 0.0,
+                    n_lanczos: int = 0, resid_tol: float = 1e-8, max_pairs: int = 0, U=None):
+    """Eigenpairs of H - iW near [e_lo, e_hi] by complex-symmetric Lanczos on
+    the device (see include/negf.h).  Returns (eps, U, resid) with U of shape
+    (n_found, N), each row normalised to U_i^T U_i = 1; U may be a
+    preallocated (max_pairs, N) torch device tensor."""
+    n_lanczos = int(n_lanczos) if n_lanczos else op.N
+    max_pairs = int(max_pairs) if max_pairs else n_lanczos
+    eps = np.zeros(max_pairs, np.complex128)
+    res = np.zeros(max_pairs)
+    if U is None:
+        U = np.zeros((max_pairs, op.N), np.complex128)
+    n = C.c_int32(0)
+    _check(_lib().negf_eigenpairs(op.handle, float(e_lo), float(e_hi), float(margin), n_lanczos,
+                                  float(resid_tol), max_pairs, _ptr(eps), _ptr(U), _ptr(res),
+                                  C.byref(n)))
+    k = n.value
+    return eps[:k], U[:k], res[:k]
+
+
 def negf_current(energies, T, bias, e_fermi: float, kT: float = 0.0, stream=None):
     """Landauer current I(V) (Eq. 1, atomic units) for each bias in `bias`
     from T(E) on the energy grid, computed on the device."""

@@ -62,11 +62,6 @@ negf_status hip_fail(hipError_t e, const char* what, int line) {
                                                                         : NEGF_E_DEVICE;
 }
 
-#define CHK(x)                                  \
-    do {                                        \
-        negf_status _s = (x);                   \
-        if (_s != NEGF_OK) return _s;           \
-    } while (0)
 
 // Test hook: NEGF_TEST_FAIL_ALLOC=k makes the k-th workspace allocation of the
 // process fail (exercises the out-of-memory path without exhausting HBM).
@@ -1818,59 +1813,109 @@ static negf_status grad_impl(negf_op* op, const negf_opts* opts, int32_t n_e,
     make_sides(op, NEGF_DIR_RL, &sd);
     CHK(restrict_sides(d, &sd));
     const int n_cols = (int)sd.cols.size();
-    const int wmax = d.block_width ? d.block_width : 32;
-    double *d_field, *d_colw, *d_roww, *d_t;
-    double2 *d_g, *d_rhs;
+    // The forward columns g_j = A(E)^-1 e_j have right-hand sides that do not
+    // depend on E, so one multi-shift run per block of columns gives them at
+    // every energy and every grid point (all N rows kept).  The adjoint
+    // right-hand sides W_L o conj(g_j) do depend on E: those solves run in the
+    // per-energy core, energy by energy.  The block width is capped so that
+    // the forward columns of all energies take at most 8 GiB.
+    const size_t per_col = (size_t)n_e * (size_t)N * sizeof(double2);
+    const int wcap = (int)std::max<size_t>(1, ((size_t)8 << 30) / per_col);
+    const int wmax = std::min(d.block_width ? d.block_width : 32, wcap);
+    // adjoint solves of a block run in batches of up to kAdj (column, energy)
+    // items across energies: the per-energy core gives each item its own shift
+    constexpr int kAdj = 64;
+    double *d_field, *d_colw, *d_roww, *d_t, *d_fw;
+    double2 *d_gall, *d_rhs;
     CHK(ws(op, WS_ROWS, (size_t)N, &d_field));
     CHK(ws(op, WS_ROWW, (size_t)sd.n_rows, &d_roww));
-    CHK(ws(op, WS_TCOL, (size_t)2 * wmax, &d_colw));
-    d_t = d_colw + wmax;
-    CHK(ws(op, WS_GAMMA, (size_t)wmax * N, &d_g));
-    CHK(ws(op, WS_TRI, (size_t)wmax * N, &d_rhs));
+    // per item: T weight 4 W_R,j, t_j(E), field weight 4 W_R,j w_E
+    CHK(ws(op, WS_TCOL, (size_t)3 * n_e * wmax, &d_colw));
+    d_t = d_colw + (size_t)n_e * wmax;
+    d_fw = d_t + (size_t)n_e * wmax;
+    CHK(ws(op, WS_GAMMA, (size_t)n_e * wmax * N, &d_gall));
+    CHK(ws(op, WS_TRI, (size_t)kAdj * N, &d_rhs));
     HIPCHK(hipMemsetAsync(d_field, 0, N * sizeof(double), s));
     HIPCHK(hipMemcpyAsync(d_roww, sd.roww.data(), sd.n_rows * sizeof(double), hipMemcpyHostToDevice, s));
     int64_t total_iters = 0;
-    int n_bad = 0;
-    std::vector<double> ie, colw, tb;
-    for (int e = 0; e < n_e; ++e) {
-        double Te = 0.0;
-        if (weights[e] == 0.0 && !T) continue;
-        for (int c0 = 0; c0 < n_cols; c0 += wmax) {
-            const int w = std::min(wmax, n_cols - c0);
-            ie.assign(w, energies[e]);
-            colw.assign(sd.colw.begin() + c0, sd.colw.begin() + c0 + w);
-            tb.assign(w, 0.0);
-            std::vector<int> st1(w, 0), st2(w, 0);
-            PEOut po;
-            po.h_status = st1.data();
-            Defaults d64 = d;
-            d64.precision = NEGF_FP64;
-            // forward columns g_j
-            CHK(run_per_energy(op, d64, w, sd.cols.data() + c0, nullptr, ie.data(), po, &total_iters, s, &tm));
-            double2* x64 = (double2*)op->bufs[WS_X64].ptr;
-            HIPCHK(hipMemcpyAsync(d_g, x64, (size_t)w * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
-            HIPCHK(hipMemcpyAsync(d_colw, colw.data(), w * sizeof(double), hipMemcpyHostToDevice, s));
-            launch_weighted_norm(d_g, N, w, sd.row0, sd.n_rows, d_roww, d_colw, d_t, s);
-            HIPCHK(hipMemcpyAsync(tb.data(), d_t, w * sizeof(double), hipMemcpyDeviceToHost, s));
-            // adjoint right-hand sides W_L o conj(g_j) and solves with the same operator
-            launch_adjoint_rhs(d_g, N, plane, w, op->d_wl, d_rhs, s);
-            po.h_status = st2.data();
-            CHK(run_per_energy(op, d64, w, nullptr, d_rhs, ie.data(), po, &total_iters, s, &tm));
-            x64 = (double2*)op->bufs[WS_X64].ptr;
-            // 8 Re sum_j W_R,j g_j lambda_j = 2 Re sum_j (4 W_R,j) g_j lambda_j
-            launch_field(d_g, x64, N, w, d_colw, 2.0 * weights[e], d_field, s);
-            HIPCHK(hipStreamSynchronize(s));
+    int n_bad = 0, n_break = 0;
+    std::vector<double> ie, colw, fw, tb, T_acc(n_e, 0.0), f_res;
+    std::vector<int> f_st;
+    Defaults d64 = d;
+    d64.precision = NEGF_FP64;
+    bool any_e = false;
+    for (int e = 0; e < n_e; ++e) any_e = any_e || weights[e] != 0.0 || T;
+    for (int c0 = 0; c0 < n_cols && any_e; c0 += wmax) {
+        const int w = std::min(wmax, n_cols - c0);
+        const int n_it = n_e * w;  // items (e, c), e-major: the layout of d_gall
+        colw.resize(n_it);
+        fw.resize(n_it);
+        for (int e = 0; e < n_e; ++e)
             for (int c = 0; c < w; ++c) {
-                Te += tb[c];
-                if (st1[c] != NEGF_ITEM_CONVERGED || st2[c] != NEGF_ITEM_CONVERGED) ++n_bad;
+                colw[(size_t)e * w + c] = sd.colw[c0 + c];
+                fw[(size_t)e * w + c] = sd.colw[c0 + c] * weights[e];
+            }
+        HIPCHK(hipMemcpyAsync(d_colw, colw.data(), n_it * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_fw, fw.data(), n_it * sizeof(double), hipMemcpyHostToDevice, s));
+        // forward: g[e][c][:] for every energy, one multi-shift run
+        f_st.assign(w, 0);
+        f_res.assign((size_t)w * n_e, 0.0);
+        MSOut mo;
+        mo.d_out = d_gall;
+        mo.out_col_stride = N;
+        mo.out_shift_stride = (int64_t)w * N;
+        mo.h_status = f_st.data();
+        mo.h_resid = f_res.data();
+        CHK(run_multishift_block(op, d64, w, w, sd.cols.data() + c0, nullptr, energies, n_e,
+                                 nullptr, 0, (int)N, nullptr, nullptr, mo, &total_iters, s, &tm));
+        for (int e = 0; e < n_e; ++e) {
+            if (weights[e] == 0.0 && !T) continue;
+            for (int c = 0; c < w; ++c) {
+                const int fs = ms_item_status(f_res[(size_t)c * n_e + e], f_st[c], d.tol);
+                if (fs == NEGF_ITEM_BREAKDOWN) ++n_break;
+                else if (fs != NEGF_ITEM_CONVERGED) ++n_bad;
             }
         }
-        if (T) T[e] = Te;
+        // t_j(E) of every item at once
+        tb.assign(n_it, 0.0);
+        launch_weighted_norm(d_gall, N, n_it, sd.row0, sd.n_rows, d_roww, d_colw, d_t, s);
+        HIPCHK(hipMemcpyAsync(tb.data(), d_t, n_it * sizeof(double), hipMemcpyDeviceToHost, s));
+        // adjoint right-hand sides W_L o conj(g_j), solved with the same operator,
+        // over runs of items whose energy has a nonzero weight
+        for (int it0 = 0; it0 < n_it;) {
+            if (weights[it0 / w] == 0.0) {
+                ++it0;
+                continue;
+            }
+            int nb = 1;
+            while (nb < kAdj && it0 + nb < n_it && weights[(it0 + nb) / w] != 0.0) ++nb;
+            double2* d_g = d_gall + (size_t)it0 * N;
+            launch_adjoint_rhs(d_g, N, plane, nb, op->d_wl, d_rhs, s);
+            ie.resize(nb);
+            for (int b = 0; b < nb; ++b) ie[b] = energies[(it0 + b) / w];
+            std::vector<int> st2(nb, 0);
+            PEOut po;
+            po.h_status = st2.data();
+            CHK(run_per_energy(op, d64, nb, nullptr, d_rhs, ie.data(), po, &total_iters, s, &tm));
+            double2* x64 = (double2*)op->bufs[WS_X64].ptr;
+            // 8 Re sum_j W_R,j w_E g_j lambda_j = 2 Re sum_j (4 W_R,j w_E) g_j lambda_j
+            launch_field(d_g, x64, N, nb, d_fw + it0, 2.0, d_field, s);
+            for (int b = 0; b < nb; ++b) {
+                if (st2[b] == NEGF_ITEM_BREAKDOWN) ++n_break;
+                else if (st2[b] != NEGF_ITEM_CONVERGED) ++n_bad;
+            }
+            it0 += nb;
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        for (int e = 0; e < n_e; ++e)
+            for (int c = 0; c < w; ++c) T_acc[e] += tb[(size_t)e * w + c];
     }
+    if (T)
+        for (int e = 0; e < n_e; ++e) T[e] = T_acc[e];
     HIPCHK(hipMemcpyAsync(dL_dV, d_field, N * sizeof(double),
                           is_device_ptr(dL_dV) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    return final_status(n_bad, 0);
+    return final_status(n_bad, n_break);
 }
 
 extern "C" negf_status negf_transmission_grad(negf_op* op, const negf_opts* opts, int32_t n_e,

@@ -121,12 +121,19 @@ negf_status hip_fail(hipError_t e, const char* what, int line);
         if (_e != hipSuccess) return hip_fail(_e, #x, __LINE__);       \
     } while (0)
 
+#define CHK(x)                                  \
+    do {                                        \
+        negf_status _s = (x);                   \
+        if (_s != NEGF_OK) return _s;           \
+    } while (0)
+
 // workspace slots
 enum WorkSlot {
     WS_R = 0, WS_P, WS_Q, WS_X, WS_B, WS_R64, WS_X64, WS_Q64,
     WS_PART, WS_PART2, WS_PART3, WS_KBC, WS_SHIFT, WS_COLJ,
     WS_STATE, WS_HIST, WS_PI, WS_GAMMA, WS_TRI, WS_TPART, WS_TCOL, WS_ROWS,
-    WS_ROWW, WS_RING, WS_XS, WS_PS, WS_COEF, WS_MISC, WS_SINK, WS_SLOTS, WS_QMRD, WS_COUNT
+    WS_ROWW, WS_RING, WS_XS, WS_PS, WS_COEF, WS_MISC, WS_SINK, WS_SLOTS, WS_QMRD,
+    WS_LANCZOS, WS_EIGTMP, WS_EIGOUT, WS_COUNT
 };
 negf_status ws_get(negf_op* op, int slot, size_t bytes, void** out);
 

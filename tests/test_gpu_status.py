@@ -1,0 +1,144 @@
+"""Failure paths and per-item diagnostics of the C ABI.
+
+* a right-hand side whose bilinear form vanishes (b^T b = 0 with b != 0)
+  cannot start COCG: NEGF_E_BREAKDOWN for that item, the others converge;
+* a 200-point chain with 80-plane absorbing regions at energies inside its
+  band, hostile to COCG (residual spikes of several orders): every item the
+  library reports converged matches the oracle, every other one is flagged,
+  and the call then does not return NEGF_OK;
+* the per-item optical-theorem error and refinement steps of negf_diag;
+* the gap between the multi-shift core's residual estimate (its stopping
+  rule) and the FP64 true residual ||b - A x|| / ||b|| on the 32x32x192 wire.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import left_support, make_custom, make_wire, rhs_columns
+
+pytestmark = pytest.mark.gpu
+
+FORMS = [("multishift", "fp64"), ("per_energy", "fp64"), ("per_energy", "mixed")]
+
+
+def _opts(P, core, prec):
+    return dict(core=P.NEGF_CORE_MULTISHIFT if core == "multishift" else P.NEGF_CORE_PER_ENERGY,
+                precision=P.NEGF_FP64 if prec == "fp64" else P.NEGF_MIXED)
+
+
+@pytest.mark.parametrize("core,prec", FORMS)
+def test_isotropic_rhs_breaks_down(gpu_lib, core, prec):
+    import paper_1401_0782_amd as P
+    from paper_1401_0782_amd import _abi
+
+    w = make_wire(1)
+    op = P.operator_from_wire(w)
+    b = np.zeros((2, w.N), np.complex128)
+    b[0, 700] = 1.0
+    b[0, 901] = 1.0j  # b^T b = 1 + i^2 = 0
+    b[1, 1500] = 1.0
+    rows = left_support(w)[::5]
+    E = w.energies[:3]
+    with pytest.raises(P.NegfError) as exc:
+        P.negf_solve_columns(op, E, rhs_dense=b, row_idx=rows, tol=1e-12, **_opts(P, core, prec))
+    assert exc.value.status == _abi.NEGF_E_BREAKDOWN
+    out, st = P.negf_solve_columns(op, E, rhs_dense=b, row_idx=rows, tol=1e-12, check=False,
+                                   **_opts(P, core, prec))
+    assert np.all(st[:, 0] == _abi.NEGF_ITEM_BREAKDOWN)
+    assert np.all(st[:, 1] == _abi.NEGF_ITEM_CONVERGED)
+    for e, En in enumerate(E):
+        g = O.green_columns(w, En, [1500], method="dense")[:, 0]
+        assert np.abs(out[e, 1] - g[rows]).max() / np.abs(g).max() < 1e-9
+
+
+@pytest.fixture(scope="module")
+def hostile_chain():
+    w = make_custom(1, 1, 200, 0.5, 2, 80, np.linspace(10.3, 13.0, 6), w0=0.5, name="chain200")
+    cols = rhs_columns(w)
+    t_ref = np.array([O.column_transmissions(w, E, method="dense") for E in w.energies])
+    return w, cols, t_ref
+
+
+@pytest.mark.parametrize("core", ["multishift", "per_energy"])
+def test_hostile_chain_flags_what_it_does_not_solve(gpu_lib, hostile_chain, core):
+    import paper_1401_0782_amd as P
+    from paper_1401_0782_amd import _abi
+
+    w, cols, t_ref = hostile_chain
+    op = P.operator_from_wire(w)
+    T, d = P.negf_transmission(op, w.energies, n_cols=len(cols), check=False, tol=1e-12,
+                               max_iter=20000, optical=True, **_opts(P, core, "fp64"))
+    ok = d.item_status == _abi.NEGF_ITEM_CONVERGED
+    err = np.abs(d.t_col - t_ref)
+    print(f"{core}: {int((~ok).sum())} of {ok.size} items flagged "
+          f"({int((d.item_status == _abi.NEGF_ITEM_BREAKDOWN).sum())} breakdowns); "
+          f"max |dt| of converged items {err[ok].max() if ok.any() else 0:.2e}; "
+          f"max optical error of converged items {d.optical_err[ok].max() if ok.any() else 0:.2e}")
+    for e, c in zip(*np.nonzero(ok & (err > 1e-8))):
+        print(f"  converged but off: E {w.energies[e]:.2f} column {c}: iters {d.iters[e, c]}, "
+              f"resid {d.resid[e, c]:.1e}, |dt| {err[e, c]:.1e}, optical {d.optical_err[e, c]:.1e}; "
+              f"column statuses {d.item_status[:, c].tolist()}")
+    # every item reported converged is a solution: its t_j matches the oracle
+    # and its column satisfies the optical theorem
+    assert np.all(err[ok] <= 1e-8)
+    assert np.all(d.optical_err[ok] <= 1e-6)
+    if ok.all():
+        assert d.status == _abi.NEGF_OK
+        assert np.max(np.abs(T - t_ref.sum(axis=1))) <= 1e-8
+    else:
+        assert d.status in (_abi.NEGF_E_BREAKDOWN, _abi.NEGF_E_NOT_CONVERGED)
+        assert d.n_not_converged == int((~ok).sum())
+
+
+@pytest.mark.parametrize("core,prec", FORMS)
+def test_optical_error_and_refinement_steps(gpu_lib, core, prec):
+    """cfg1 wire: the optical theorem holds per item to rounding in every
+    form; the multi-shift core does no refinement, the FP64 per-energy core
+    one pass, the mixed core at least two (FP32 inner solves to 2e-6 against
+    an FP64 tolerance of 1e-12)."""
+    import paper_1401_0782_amd as P
+
+    w = make_wire(1)
+    op = P.operator_from_wire(w)
+    n = len(rhs_columns(w))
+    T, d = P.negf_transmission(op, w.energies, n_cols=n, tol=1e-12, optical=True,
+                               **_opts(P, core, prec))
+    assert np.all(d.item_status == 0)
+    assert np.all(np.isfinite(d.optical_err)) and d.optical_err.max() <= 1e-8, d.optical_err.max()
+    if core == "multishift":
+        assert np.all(d.refine_steps == 0)
+    elif prec == "fp64":
+        assert np.all(d.refine_steps >= 1)
+    else:
+        assert np.all(d.refine_steps >= 2)
+    # the same T with and without the optical check (it only adds kept rows)
+    T2 = P.negf_transmission(op, w.energies, tol=1e-12, **_opts(P, core, prec))
+    assert np.max(np.abs(T - T2)) <= 1e-12
+
+
+def test_multishift_true_residual_gap_full_wire(gpu_lib):
+    """32x32x192 wire: the multi-shift core stops each energy on the COCG
+    residual estimate ||r_k|| / |pi_k|.  Its FP64 true residual
+    ||e_j - A(E) x|| / ||e_j||, formed from the full-length iterates of two
+    columns at three energies with the operator apply, stays within 100x of
+    tol = 1e-10."""
+    import paper_1401_0782_amd as P
+
+    w = make_wire(2)
+    op = P.operator_from_wire(w)
+    cols = rhs_columns(w)[[9999, 15000]]
+    E = np.array([0.3, 0.55, 0.8])
+    out, st = P.negf_solve_columns(op, E, rhs_idx=cols, tol=1e-10, core=P.NEGF_CORE_MULTISHIFT,
+                                   block_width=2)
+    assert np.all(st == 0)
+    worst = 0.0
+    for e, En in enumerate(E):
+        Ax = P.negf_apply_operator(op, np.full(2, En), out[e])
+        for k, j in enumerate(cols):
+            r = -Ax[k]
+            r[j] += 1.0
+            res = np.linalg.norm(r)
+            worst = max(worst, res)
+            print(f"E {En:.2f} column {j}: true residual {res:.2e}")
+    assert worst <= 1e-8, worst
