@@ -52,7 +52,16 @@ typedef enum {
 } negf_status;
 
 /* per-item status codes written to item_status arrays */
-enum { NEGF_ITEM_CONVERGED = 0, NEGF_ITEM_MAX_ITER = 1, NEGF_ITEM_BREAKDOWN = 2 };
+enum {
+    NEGF_ITEM_CONVERGED = 0,
+    NEGF_ITEM_MAX_ITER = 1,
+    NEGF_ITEM_BREAKDOWN = 2,
+    /* the residual test passed but the optical-theorem check (negf_diag.
+       optical_err, when requested) failed: error above max(1e4 tol, 1e-8).
+       The multi-shift core stops on the COCG residual estimate, which on
+       hard systems can drift far from the true residual */
+    NEGF_ITEM_INACCURATE = 3
+};
 
 /* negf_opts.precision */
 enum {
@@ -149,7 +158,8 @@ typedef struct {
                                 |sum_i W_i |g_ij|^2 + Im g_jj| / |Im g_jj| over both
                                 absorbing regions.  Requesting it makes the
                                 multi-shift core also keep the source side's rows
-                                (twice the kept rows) */
+                                (twice the kept rows), and items above
+                                max(1e4 tol, 1e-8) report NEGF_ITEM_INACCURATE */
     int32_t* refine_steps;   /* per item, outer refinement steps of the per-energy
                                 core (0 in the multi-shift core) */
 } negf_diag;

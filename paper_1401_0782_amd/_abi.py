@@ -16,7 +16,7 @@ NEGF_E_BREAKDOWN = 5
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE",
                 4: "NOT_CONVERGED", 5: "BREAKDOWN"}
 
-NEGF_ITEM_CONVERGED, NEGF_ITEM_MAX_ITER, NEGF_ITEM_BREAKDOWN = 0, 1, 2
+NEGF_ITEM_CONVERGED, NEGF_ITEM_MAX_ITER, NEGF_ITEM_BREAKDOWN, NEGF_ITEM_INACCURATE = 0, 1, 2, 3
 NEGF_FP64, NEGF_MIXED = 0, 1
 NEGF_CORE_AUTO, NEGF_CORE_PER_ENERGY, NEGF_CORE_MULTISHIFT = 0, 1, 2
 NEGF_DIR_RL, NEGF_DIR_LR = 0, 1

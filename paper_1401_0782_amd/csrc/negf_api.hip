@@ -724,6 +724,7 @@ static int shift_chunk(const negf_op* op) { return op->N >= 131072 ? 256 : 128; 
 // column flags, and after_chunk() does the host bookkeeping once that chunk
 // has finished (chunk_done() polls it without blocking).  One host thread
 // can so keep the streams of many runs busy (the junction batch).
+template <typename R>
 class MultiShiftRun {
   public:
     MultiShiftRun(negf_op* op, const Defaults& d, int w, int n_src, const int* cols,
@@ -778,7 +779,12 @@ class MultiShiftRun {
 
     int64_t N_ = 0;
     int nblk_ = 0, ch_ = 0, ring_len_ = 0;
-    double2 *r_ = nullptr, *p_ = nullptr, *p2_ = nullptr, *q_ = nullptr, *part_ = nullptr;
+    // the seed's Krylov vectors in R; the ring, the shifted iterates and
+    // every scalar are FP64.  Only R = double is instantiated: with FP32
+    // seed vectors no energy of the 32x32x192 wire converged within 100,000
+    // iterations (the shifted recurrences inherit the FP32 seed's drift)
+    cplx_t<R> *r_ = nullptr, *p_ = nullptr, *p2_ = nullptr, *q_ = nullptr;
+    double2 *part_ = nullptr;
     double2 *kbc_ = nullptr, *ring_ = nullptr, *X_ = nullptr, *P_ = nullptr, *part_f_ = nullptr;
     double *part_nn_ = nullptr, *shift_ = nullptr;
     int* d_cols_ = nullptr;
@@ -806,7 +812,8 @@ class MultiShiftRun {
     bool use_graph_ = true;
 };
 
-negf_status MultiShiftRun::start() {
+template <typename R>
+negf_status MultiShiftRun<R>::start() {
     negf_op* op = op_;
     const int w = w_, ng = ng_, n_rows = n_rows_;
     hipStream_t s = s_;
@@ -895,16 +902,16 @@ negf_status MultiShiftRun::start() {
     if (cols_) {
         for (int c = 0; c < w; ++c) h_colsel_[c] = cols_[c];
         HIPCHK(hipMemcpyAsync(d_cols_, h_colsel_.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
-        launch_init_unit<double>(r_, nullptr, N, w, d_cols_, s);
+        launch_init_unit<R>(r_, nullptr, N, w, d_cols_, s);
     } else {
         HIPCHK(hipMemcpyAsync(r_, d_rhs_, (size_t)w * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
     }
     HIPCHK(hipMemsetAsync(X_, 0, (size_t)w * ng * n_rows * sizeof(double2), s));
     HIPCHK(hipMemsetAsync(P_, 0, (size_t)w * ng * n_rows * sizeof(double2), s));
     HIPCHK(hipMemsetAsync(carry_, 0, (size_t)w * ng * sizeof(double2), s));
-    launch_norms<double>(r_, N, w, nullptr, part_, part_nn_, s);
+    launch_norms<R>(r_, N, w, nullptr, part_, part_nn_, s);
     launch_reduce_init(part_, part_nn_, nblk_, st_, nullptr, s);
-    launch_store_rows<double>(r_, N, w, d_rows_, row0_, n_rows, ring_, ring_len_, st_, 0, s,
+    launch_store_rows<R>(r_, N, w, d_rows_, row0_, n_rows, ring_, ring_len_, st_, 0, s,
                               nullptr, out_.row1, out_.n_rows1);
     HIPCHK(hipGetLastError());
 
@@ -929,7 +936,8 @@ negf_status MultiShiftRun::start() {
     return NEGF_OK;
 }
 
-negf_status MultiShiftRun::issue_chunk() {
+template <typename R>
+negf_status MultiShiftRun<R>::issue_chunk() {
     negf_op* op = op_;
     const int w = w_;
     const int64_t N = N_;
@@ -957,15 +965,15 @@ negf_status MultiShiftRun::issue_chunk() {
         for (int it = 0; it < steps; ++it) {
             // p ping-pongs so that halo reads of the fused kernel see p_{k-1};
             // every column starts at an even k
-            double2* pin = (it & 1) ? p2_ : p_;
-            double2* pout = (it & 1) ? p_ : p2_;
+            cplx_t<R>* pin = (it & 1) ? p2_ : p_;
+            cplx_t<R>* pout = (it & 1) ? p_ : p2_;
             hipEvent_t e0, e1;
             CHK(tm->next(&e0, &e1));
-            launch_cocg_apply<double>(op, r_, pin, pout, q_, w, shift_, st_.done, st_.k, st_.beta,
+            launch_cocg_apply<R>(op, r_, pin, pout, q_, w, shift_, st_.done, st_.k, st_.beta,
                                       part_f_, kbc_, s, e0, e1, !fused_update_, w_geom);
             if (fused_update_) {
                 // alpha, projector term, r update and kept rows in one launch
-                launch_update_ms<double>(r_, q_, N, st_, part_f_, nblk_f, op, kbc_, ring_,
+                launch_update_ms<R>(r_, q_, N, st_, part_f_, nblk_f, op, kbc_, ring_,
                                          ring_len_, row0_, n_rows_, part_, part_nn_, s,
                                          out_.row1, out_.n_rows1);
                 launch_reduce_beta_multishift(part_, part_nn_, nblk_, st_, s);
@@ -973,8 +981,8 @@ negf_status MultiShiftRun::issue_chunk() {
             }
             launch_reduce_alpha(part_f_, nblk_f, st_, s, op->kb.n_proj ? kbc_ : nullptr,
                                 op->kb.e, op->kb.n_proj);
-            launch_r_update<double>(r_, q_, nullptr, nullptr, part_, part_nn_, st_, N, s);
-            launch_store_rows<double>(r_, N, w, d_rows_, row0_, n_rows_, ring_, ring_len_, st_, 1, s,
+            launch_r_update<R>(r_, q_, nullptr, nullptr, part_, part_nn_, st_, N, s);
+            launch_store_rows<R>(r_, N, w, d_rows_, row0_, n_rows_, ring_, ring_len_, st_, 1, s,
                                       nullptr, out_.row1, out_.n_rows1);
             launch_reduce_beta_multishift(part_, part_nn_, nblk_, st_, s);
         }
@@ -1000,7 +1008,8 @@ negf_status MultiShiftRun::issue_chunk() {
     return NEGF_OK;
 }
 
-negf_status MultiShiftRun::after_chunk(bool* busy) {
+template <typename R>
+negf_status MultiShiftRun<R>::after_chunk(bool* busy) {
     negf_op* op = op_;
     const int w = w_, ng = ng_, n_rows = n_rows_;
     const int64_t N = N_;
@@ -1015,7 +1024,7 @@ negf_status MultiShiftRun::after_chunk(bool* busy) {
         // p_{k-1} in, p_k and q out; V once per launch
         int64_t ci = 0;
         for (int c = 0; c < w; ++c) ci += h_k[c] - h_kprev_[c];
-        tm->bytes += 4.0 * sizeof(double2) * (double)N * (double)ci + 8.0 * N * steps_;
+        tm->bytes += 4.0 * sizeof(cplx_t<R>) * (double)N * (double)ci + 8.0 * N * steps_;
     }
     for (int c = 0; c < w; ++c) h_kprev_[c] = h_k[c];
     const bool stop = (n_src_ == w) && launches_ >= d_.max_iter;
@@ -1090,7 +1099,7 @@ negf_status MultiShiftRun::after_chunk(bool* busy) {
         HIPCHK(hipMemcpyAsync(d_mask_, h_mask_.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(d_notmask_, h_notmask_.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(d_cols_, h_colsel_.data(), w * sizeof(int), hipMemcpyHostToDevice, s));
-        launch_init_unit<double>(r_, nullptr, N, w, d_cols_, s, d_mask_);
+        launch_init_unit<R>(r_, nullptr, N, w, d_cols_, s, d_mask_);
         for (int c = 0; c < w; ++c)
             if (h_mask_[c]) h_kprev_[c] = 0;
         for (int c = 0; c < w; ++c) {
@@ -1100,9 +1109,9 @@ negf_status MultiShiftRun::after_chunk(bool* busy) {
             HIPCHK(hipMemsetAsync(P_ + xo, 0, (size_t)ng * n_rows * sizeof(double2), s));
             HIPCHK(hipMemsetAsync(carry_ + (size_t)c * ng, 0, (size_t)ng * sizeof(double2), s));
         }
-        launch_norms<double>(r_, N, w, d_notmask_, part_, part_nn_, s);
+        launch_norms<R>(r_, N, w, d_notmask_, part_, part_nn_, s);
         launch_reduce_init(part_, part_nn_, nblk_, st_, nullptr, s, d_mask_);
-        launch_store_rows<double>(r_, N, w, d_rows_, row0_, n_rows, ring_, ring_len_, st_, 0, s,
+        launch_store_rows<R>(r_, N, w, d_rows_, row0_, n_rows, ring_, ring_len_, st_, 0, s,
                                   d_mask_, out_.row1, out_.n_rows1);
         HIPCHK(hipGetLastError());
     }
@@ -1118,7 +1127,8 @@ negf_status MultiShiftRun::after_chunk(bool* busy) {
     return NEGF_OK;
 }
 
-negf_status MultiShiftRun::finish() {
+template <typename R>
+negf_status MultiShiftRun<R>::finish() {
     const int w = w_, ng = ng_, n_rows = n_rows_;
     hipStream_t s = s_;
     if (gemm_pending_) HIPCHK(hipStreamWaitEvent(s, ev_gemm_, 0));
@@ -1148,15 +1158,18 @@ static negf_status run_multishift_block(negf_op* op, const Defaults& d, int w, i
                                         int64_t row0, int n_rows, const double* d_row_w,
                                         const double* h_col_w, const MSOut& out,
                                         int64_t* total_iters, hipStream_t s, MatvecTimer* tm) {
-    MultiShiftRun run(op, d, w, n_src, cols, d_rhs, energies, ng, d_rows, row0, n_rows, d_row_w,
-                      h_col_w, out, total_iters, s, tm);
-    CHK(run.start());
-    bool busy = true;
-    while (busy) {
-        CHK(run.issue_chunk());
-        CHK(run.after_chunk(&busy));
-    }
-    return run.finish();
+    auto go = [&](auto& run) -> negf_status {
+        CHK(run.start());
+        bool busy = true;
+        while (busy) {
+            CHK(run.issue_chunk());
+            CHK(run.after_chunk(&busy));
+        }
+        return run.finish();
+    };
+    MultiShiftRun<double> run(op, d, w, n_src, cols, d_rhs, energies, ng, d_rows, row0, n_rows,
+                              d_row_w, h_col_w, out, total_iters, s, tm);
+    return go(run);
 }
 
 // launchers of adjoint.hip
@@ -1597,6 +1610,13 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
                 if (want_opt) optical[o] = b_o[c];
             }
         }
+    }
+    // the optical-theorem check, when computed, must also hold
+    if (want_opt) {
+        const double opt_bar = std::max(1e4 * d.tol, 1e-8);
+        for (size_t o = 0; o < status.size(); ++o)
+            if (status[o] == NEGF_ITEM_CONVERGED && !(optical[o] <= opt_bar))
+                status[o] = NEGF_ITEM_INACCURATE;
     }
     int n_bad = 0, n_break = 0;
     for (int e = 0; e < n_e; ++e) {
@@ -2278,7 +2298,7 @@ struct BatchJob {
     std::vector<int> blk_it, blk_st, blk_si;
     int64_t total_iters = 0;
     MatvecTimer tm;
-    std::unique_ptr<MultiShiftRun> run;
+    std::unique_ptr<MultiShiftRun<double>> run;
 };
 
 // Whether junction i of the batch runs as one resumable multi-shift run (FP64
@@ -2317,7 +2337,7 @@ static negf_status batch_job_start(BatchJob* job, const negf_opts* opts, const d
     mo.h_resid = job->blk_r.data();
     mo.h_shift_iters = job->blk_si.data();
     CHK(job->tm.init(0));
-    job->run = std::make_unique<MultiShiftRun>(op, job->d, w, n_cols, job->sd.cols.data(), nullptr,
+    job->run = std::make_unique<MultiShiftRun<double>>(op, job->d, w, n_cols, job->sd.cols.data(), nullptr,
                                                energies, ng, nullptr, job->sd.row0, job->sd.n_rows,
                                                d_roww, job->sd.colw.data(), mo, &job->total_iters,
                                                s, &job->tm);

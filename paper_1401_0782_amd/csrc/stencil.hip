@@ -364,11 +364,25 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
     cplx_t<R>* __restrict__ y, int nx, int ny, int nz, int ty, int n_ytiles, int zchunk,
     Coef<R> cf, double a0, const double* __restrict__ v, const double* __restrict__ wz,
     const double* __restrict__ shift, const int* __restrict__ skip, const int* __restrict__ kit,
-    const double2* __restrict__ beta, double2* __restrict__ part) {
+    const double2* __restrict__ beta, double2* __restrict__ part, int xcd_group) {
     extern __shared__ unsigned char smem_raw[];
-    const int c = blockIdx.y;
+    // launch index -> (tile, column).  The y-tiles of one z-chunk read each
+    // other's boundary rows as halo at the same plane and time; with
+    // xcd_group the G work-groups are dealt to the 8 XCDs in turn (work-group
+    // i goes to XCD i mod 8) so that the i-th one an XCD receives takes
+    // logical index xcd * (G / 8) + i: consecutive tiles share an XCD and the
+    // halo rows come from its L2
+    const int nb = gridDim.x;
+    int bid = blockIdx.x, c = blockIdx.y;
+    if (xcd_group) {
+        const int G = nb * gridDim.y;
+        const int lin = blockIdx.x + nb * blockIdx.y;
+        const int G8 = G & ~7;
+        const int logical = lin < G8 ? (lin & 7) * (G8 >> 3) + (lin >> 3) : lin;
+        bid = logical % nb;
+        c = logical / nb;
+    }
     if (skip && skip[c]) return;
-    const int bid = blockIdx.x;
     const int ytile = bid % n_ytiles;
     const int z0 = (bid / n_ytiles) * zchunk;
     const int z1 = min(nz, z0 + zchunk);
@@ -533,7 +547,7 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
                 sx += red[2 * wv];
                 sy += red[2 * wv + 1];
             }
-            part[(int64_t)c * gridDim.x + bid] = make_double2(sx, sy);
+            part[(int64_t)c * nb + bid] = make_double2(sx, sy);
         }
     }
 }
@@ -773,11 +787,17 @@ void fused_launch(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin, c
                            part);
         return;
     }
+    // y-tiles of a z-chunk grouped on one XCD; NEGF_ROWTILE_XCD=0 deals them
+    // out in launch order instead (A/B measurement)
+    static const int xcd_group = [] {
+        const char* e = getenv("NEGF_ROWTILE_XCD");
+        return (e && e[0] == '0') ? 0 : 1;
+    }();
     auto go = [&](auto kern, int nt) {
         if (g.lds > 65536) allow_large_lds((const void*)kern);
         hipLaunchKernelGGL(kern, grid, dim3(nt), g.lds, s, r, pin, pout, y, op->nx, op->ny,
                            op->nz, g.ty, g.n_ytiles, g.zchunk, cf, op->coef.a[0], op->d_v,
-                           op->d_wz, shift, skip, kit, beta, part);
+                           op->d_wz, shift, skip, kit, beta, part, g.n_ytiles > 1 ? xcd_group : 0);
     };
     if (g.nt == 256)
         go(k_cocg_apply<RAD, R, 256, FUSED>, 256);

@@ -3,9 +3,11 @@
 * a right-hand side whose bilinear form vanishes (b^T b = 0 with b != 0)
   cannot start COCG: NEGF_E_BREAKDOWN for that item, the others converge;
 * a 200-point chain with 80-plane absorbing regions at energies inside its
-  band, hostile to COCG (residual spikes of several orders): every item the
-  library reports converged matches the oracle, every other one is flagged,
-  and the call then does not return NEGF_OK;
+  band, hostile to COCG (residual spikes of several orders, tens of thousands
+  of iterations, recursive and true residuals drifting apart): with the
+  optical-theorem check requested, every item the library reports converged
+  matches the oracle, every other one is flagged, and the call then does not
+  return NEGF_OK;
 * the per-item optical-theorem error and refinement steps of negf_diag;
 * the gap between the multi-shift core's residual estimate (its stopping
   rule) and the FP64 true residual ||b - A x|| / ||b|| on the 32x32x192 wire.
@@ -80,9 +82,12 @@ def test_hostile_chain_flags_what_it_does_not_solve(gpu_lib, hostile_chain, core
               f"resid {d.resid[e, c]:.1e}, |dt| {err[e, c]:.1e}, optical {d.optical_err[e, c]:.1e}; "
               f"column statuses {d.item_status[:, c].tolist()}")
     # every item reported converged is a solution: its t_j matches the oracle
-    # and its column satisfies the optical theorem
+    # and its column satisfies the optical theorem to the library's bar
+    # max(1e4 tol, 1e-8); those that fail only that check are INACCURATE
     assert np.all(err[ok] <= 1e-8)
-    assert np.all(d.optical_err[ok] <= 1e-6)
+    assert np.all(d.optical_err[ok] <= 1e-8)
+    inacc = d.item_status == _abi.NEGF_ITEM_INACCURATE
+    assert np.all(d.optical_err[inacc] > 1e-8)
     if ok.all():
         assert d.status == _abi.NEGF_OK
         assert np.max(np.abs(T - t_ref.sum(axis=1))) <= 1e-8
