@@ -1,11 +1,12 @@
-"""CAP variants through the C ABI: the Gaussian of Eq. 5 and monomial ramps,
-against the oracle, and the calibration plateau on an empty lead."""
+"""CAP variants through the C ABI: the Gaussian of Eq. 5, monomial ramps and
+the Riss-Meyer-tuned monomial CAP, against the oracle, and the calibration
+plateau on an empty lead."""
 
 import numpy as np
 import pytest
 
 import oracle as O
-from workloads import end_gaussian_cap, make_custom, power_cap, with_caps
+from workloads import end_gaussian_cap, make_custom, power_cap, riss_meyer_cap, with_caps
 
 pytestmark = pytest.mark.gpu
 
@@ -21,6 +22,16 @@ def _mids():
     return mids, np.array([np.count_nonzero(thr < E) for E in mids])
 
 
+def _riss_meyer(order):
+    """Tuned to the longitudinal kinetic energies of every open channel at
+    the test energies."""
+    mids, _ = _mids()
+    thr = O.transverse_thresholds(NX, NY, H, R)
+    ek = np.concatenate([m - thr[thr < m] for m in mids])
+    left, right, _ = riss_meyer_cap(NZ, H, NCAP, ek.min(), ek.max(), order)
+    return left, right
+
+
 CAPS = {
     "gauss_w1_s8": lambda: end_gaussian_cap(NZ, H, NCAP, 8.0, 1.0),
     "gauss_w2_s8": lambda: end_gaussian_cap(NZ, H, NCAP, 8.0, 2.0),
@@ -28,6 +39,8 @@ CAPS = {
     "gauss_w2_s9.84": lambda: end_gaussian_cap(NZ, H, NCAP, 9.84, 2.0),
     "power2": lambda: power_cap(NZ, NCAP, 2.0, 2),
     "power4": lambda: power_cap(NZ, NCAP, 2.0, 4),
+    "riss_meyer2": lambda: _riss_meyer(2),
+    "riss_meyer3": lambda: _riss_meyer(3),
 }
 
 
@@ -44,6 +57,8 @@ def test_cap_variant_matches_oracle_and_mode_count(gpu_lib, cap, core):
     T_ref = O.transmission(wire, mids, method="dense")
     assert np.max(np.abs(T - T_ref)) <= 1e-8
     assert np.max(np.abs(T - expect)) < 5e-4
+    if cap.startswith("riss_meyer"):  # the tuned CAP absorbs far better
+        assert np.max(np.abs(T - expect)) < 2e-6
 
 
 def test_gaussian_cap_on_a_wire_with_projectors(gpu_lib):

@@ -20,5 +20,8 @@ from .wires import (  # noqa: F401
     quartic_cap,
     power_cap,
     end_gaussian_cap,
+    riss_meyer_cap,
+    riss_meyer_error,
+    riss_meyer_strength,
     with_caps,
 )

@@ -26,6 +26,7 @@ Conventions (all stated once here, used everywhere):
 from __future__ import annotations
 
 import dataclasses
+import math
 from typing import Optional
 
 import numpy as np
@@ -104,6 +105,59 @@ def end_gaussian_cap(nz: int, h: float, n_cap: int, sigma: float, w0: float):
     left = np.where(z < n_cap, w0 * np.exp(-((z * h) ** 2) / sigma ** 2), 0.0)
     right = np.where(z >= nz - n_cap, w0 * np.exp(-(((nz - 1 - z) * h) ** 2) / sigma ** 2), 0.0)
     return left, right
+
+
+def riss_meyer_strength(length: float, order: int, e_kin_lo: float, e_kin_hi: float) -> float:
+    """Strength eta of a monomial CAP W(z) = eta (z / length)^order, 0 <= z <=
+    length, tuned to a window of longitudinal kinetic energies in the way
+    Riss and Meyer analyse such CAPs (the reference the paper gives, in its
+    outlook, for a more efficient absorber than Eq. 5): in atomic units,
+    a wave of wavenumber k is
+      * reflected at the CAP's onset with the first-order (Born) amplitude
+        |r| = eta order! / (k length^order (2k)^(order+1)), largest at the
+        low end of the window;
+      * transmitted through the CAP, reflected by the box end and returned
+        with weight exp(-4 eta length / ((order + 1) k)) (WKB), largest at
+        the high end.
+    eta balances the two worst cases, |r(k_lo)|^2 = exp(...)(k_hi), which
+    minimises the larger of them (one rises with eta, the other falls)."""
+    if not (length > 0 and order >= 1 and 0 < e_kin_lo < e_kin_hi):
+        raise ValueError("need length > 0, order >= 1 and 0 < e_kin_lo < e_kin_hi")
+    k_lo, k_hi = math.sqrt(2.0 * e_kin_lo), math.sqrt(2.0 * e_kin_hi)
+    fact = math.factorial(order)
+
+    def gap(log_eta):  # log reflection(k_lo) - log round trip(k_hi)
+        eta = math.exp(log_eta)
+        log_r2 = 2.0 * (math.log(eta * fact) - math.log(k_lo) - order * math.log(length)
+                        - (order + 1) * math.log(2.0 * k_lo))
+        log_t = -4.0 * eta * length / ((order + 1) * k_hi)
+        return log_r2 - log_t
+
+    lo, hi = math.log(1e-12), math.log(1e12)
+    for _ in range(200):  # bisection: gap rises monotonically with eta
+        mid = 0.5 * (lo + hi)
+        if gap(mid) > 0.0:
+            hi = mid
+        else:
+            lo = mid
+    return math.exp(0.5 * (lo + hi))
+
+
+def riss_meyer_error(length: float, order: int, eta: float, e_kin: float) -> float:
+    """The two estimates above at one kinetic energy, summed: |r|^2 + round trip."""
+    k = math.sqrt(2.0 * e_kin)
+    r = eta * math.factorial(order) / (k * length ** order * (2.0 * k) ** (order + 1))
+    return r * r + math.exp(-4.0 * eta * length / ((order + 1) * k))
+
+
+def riss_meyer_cap(nz: int, h: float, n_cap: int, e_kin_lo: float, e_kin_hi: float,
+                   order: int = 2):
+    """Monomial CAP on the n_cap end planes (onset one plane inside, length
+    n_cap h) with the strength riss_meyer_strength picks for the window;
+    returns (left, right, eta)."""
+    eta = riss_meyer_strength(n_cap * h, order, e_kin_lo, e_kin_hi)
+    left, right = power_cap(nz, n_cap, eta, order)
+    return left, right, eta
 
 
 def with_caps(wire, left, right, name=None):
