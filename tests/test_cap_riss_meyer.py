@@ -1,7 +1,8 @@
 """The Riss-Meyer-tuned monomial CAP (the more efficient absorber the paper
-points to in its outlook, Sec. IV) on an empty 1-D chain, where the exact
-transmission of the single channel is 1 at every energy of the band: the
-oracle's T(E) (dense inversion of Eq. 7) then measures the CAP's own error.
+points to among its future work, Sec. III.E) on an empty 1-D chain, where
+the exact transmission of the single channel is 1 at every energy of the
+band: the oracle's T(E) (dense inversion of Eq. 7) then measures the CAP's
+own error.
 
 * with the strength the estimates pick for a window of kinetic energies,
   max |T - 1| over the window stays within twice the estimated amplitude

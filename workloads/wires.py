@@ -110,8 +110,8 @@ def end_gaussian_cap(nz: int, h: float, n_cap: int, sigma: float, w0: float):
 def riss_meyer_strength(length: float, order: int, e_kin_lo: float, e_kin_hi: float) -> float:
     """Strength eta of a monomial CAP W(z) = eta (z / length)^order, 0 <= z <=
     length, tuned to a window of longitudinal kinetic energies in the way
-    Riss and Meyer analyse such CAPs (the reference the paper gives, in its
-    outlook, for a more efficient absorber than Eq. 5): in atomic units,
+    Riss and Meyer analyse such CAPs (the reference the paper gives, in
+    Sec. III.E, for a more efficient absorber than Eq. 5): in atomic units,
     a wave of wavenumber k is
       * reflected at the CAP's onset with the first-order (Born) amplitude
         |r| = eta order! / (k length^order (2k)^(order+1)), largest at the
