@@ -23,6 +23,7 @@ import json
 import multiprocessing as mp
 import os
 import pathlib
+import re
 import sys
 import time
 
@@ -41,9 +42,37 @@ LAUNCH_SHAPE = (192, 1)
 COUNTERS = ROOT / "profiles" / "stencil_wire32x32x192_counters.txt"
 GOLDEN = ROOT / "tests" / "golden" / "wire32x32x192_samples.json"
 KERNEL_SRC = ROOT / "paper_1401_0782_amd" / "csrc" / "stencil.hip"
+KERNEL_HELPERS = ROOT / "paper_1401_0782_amd" / "csrc" / "negf_internal.h"
 
 
 KERNELS = {1: "k_cocg_plane<6,double,true>", 0: "k_cocg_apply<6,double,1024,true>"}
+
+
+def _function_text(src, name):
+    """The source of the function (or function template) called name: from
+    its template line, or its own line, through the first closing brace at
+    column 0; None if the source has no such function."""
+    m = re.search(r"^(template <[^\n]*>\n)?[^\n]*\b%s\(" % re.escape(name), src, re.M)
+    if not m:
+        return None
+    end = src.find("\n}\n", m.start())
+    return src[m.start(): end + 3 if end >= 0 else len(src)]
+
+
+def kernel_source_hash(kernel):
+    """16 hex digits of sha256 over the source the counters depend on: the
+    stencil kernel's own function, the function that sets its launch geometry
+    and the load / store helpers it calls.  Edits elsewhere in the stencil
+    source (the other kernel, comments) leave it unchanged."""
+    name = kernel.split("<", 1)[0]
+    src = KERNEL_SRC.read_text()
+    parts = [_function_text(src, name), _function_text(src, "fused_geom")]
+    if KERNEL_HELPERS.exists():
+        helpers = KERNEL_HELPERS.read_text()
+        parts += [_function_text(helpers, "ld_once"), _function_text(helpers, "st_once")]
+    if parts[0] is None:  # no such kernel: the whole file stands for it
+        parts = [src]
+    return hashlib.sha256("".join(p or "" for p in parts).encode()).hexdigest()[:16]
 
 
 def _traffic_from_profile(kernel, shape):
@@ -58,11 +87,10 @@ def _traffic_from_profile(kernel, shape):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             fields[k.strip()] = v.strip()
-    src_hash = hashlib.sha256(KERNEL_SRC.read_bytes()).hexdigest()[:16]
-    if fields.get("stencil_src_sha256_16") != src_hash:
-        return None, "counters predate the current stencil source"
     if fields.get("kernel") != kernel:
         return None, f"counters were taken on {fields.get('kernel')}, this run used {kernel}"
+    if fields.get("kernel_src_sha256_16") != kernel_source_hash(kernel):
+        return None, "counters predate the current kernel source"
     tag = f"{shape[0]},{shape[1]}"
     key = ("traffic_over_algorithmic" if fields.get("launch_shape") == tag
            else f"traffic_over_algorithmic_at_{shape[0]}_{shape[1]}")
@@ -185,7 +213,7 @@ def cpu_baseline(seconds: float):
 
 # ---------------------------------------------------------- secondary rows
 FP64_PEAK_TFS = 78.6
-ROWS = ("small", "batch", "full", "adjoint", "large", "spectral", "current")
+ROWS = ("small", "mixed", "batch", "full", "adjoint", "large", "spectral", "current", "copy")
 
 
 def measure_rows(names):
@@ -210,6 +238,30 @@ def measure_rows(names):
         return out, time.perf_counter() - t
 
     for name in names:
+        if name == "copy":
+            # the practical HBM ceiling the stencil's fraction is read against:
+            # torch's device copy (one read, one write) and a two-input add (two
+            # reads, one write, the stencil's read/write mix), 4 GiB per operand
+            n = 1 << 28
+            a = torch.ones(n, dtype=torch.complex128, device="cuda")
+            b = torch.ones_like(a)
+            c = torch.empty_like(a)
+            for form, fn, n_moved in [("copy", lambda: c.copy_(a), 2),
+                                      ("add", lambda: torch.add(a, b, out=c), 3)]:
+                fn()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                reps = 10
+                e0.record()
+                for _ in range(reps):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                sec = e0.elapsed_time(e1) / 1e3 / reps
+                emit(row=name, form=form, bytes_per_call=n_moved * a.numel() * 16,
+                     seconds_per_call=sec, gb_per_s=n_moved * a.numel() * 16 / sec / 1e9)
+            del a, b, c
+            torch.cuda.empty_cache()
+            continue
         if name == "small":
             w = make_wire(1)
             op = P.operator_from_wire(w)
@@ -228,6 +280,34 @@ def measure_rows(names):
                 T, t = timed(lambda: P.negf_transmission(op, E, tol=TOL, **kw))
                 emit(row=name, form=form, seconds=t, solves_per_s=n * E.size / t,
                      max_dT_vs_core_B=float(np.abs(T - ref).max()))
+        elif name == "mixed":
+            # the precision form: mixed (FP32 vectors, FP64 scalars, FP64 true
+            # residual and refinement) against FP64 in the same per-energy
+            # core and against the best FP64 form (multi-shift); each line as
+            # soon as its form has run
+            for wid, cols, ne in ((1, None, None), (2, 16, 4)):
+                w = make_wire(wid)
+                op = P.operator_from_wire(w)
+                n_all = len(rhs_columns(w))
+                n = cols or n_all
+                E = w.energies if ne is None else w.energies[np.linspace(0, w.energies.size - 1,
+                                                                         ne).astype(int)]
+                kw = dict(tol=TOL, col_begin=0, col_count=n)
+                ref = {}
+                for form, fk in [("core B FP64", dict(core=P.NEGF_CORE_MULTISHIFT)),
+                                 ("core A FP64", dict(core=P.NEGF_CORE_PER_ENERGY)),
+                                 ("core A mixed", dict(precision=P.NEGF_MIXED))]:
+                    (T, d), t = timed(lambda: P.negf_transmission(op, E, n_cols=n, check=False,
+                                                                   **kw, **fk))
+                    ref.setdefault(form, (T, t))
+                    T0, tB = ref["core B FP64"]
+                    tA = ref.get("core A FP64", (None, t))[1]
+                    emit(row=name, workload=f"{w.name}, {n} cols x {E.size} E", form=form,
+                         seconds=t, solves_per_s=n * E.size / t,
+                         column_iterations=d.total_iters, status=int(d.status),
+                         median_item_iterations=float(np.median(d.iters)),
+                         speed_vs_core_A_fp64=tA / t, speed_vs_core_B_fp64=tB / t,
+                         max_dT_vs_core_B_fp64=float(np.abs(T - T0).max()))
         elif name == "batch":
             js = make_junctions(64)
             ops = [P.operator_from_wire(j) for j in js]
@@ -272,7 +352,23 @@ def measure_rows(names):
             (_, d), t = timed(run)  # one 16-column block of ~50 s: not repeated
             emit(row=name, workload=f"wire 64x64x256 R=6 KB, {cols} cols x {E.size} E",
                  form="core B FP64 (cold)", seconds=t, solves_per_s=cols * E.size / t,
-                 status=int(d.status))
+                 column_iterations_per_s=d.total_iters / t, status=int(d.status))
+            # wider blocks: the kept-row accumulators X, P of every energy take
+            # 2 w n_E n_rows 16 B (86 GB at w = 32; 128 columns would need 343
+            # GB), and a whole 32-column block would run ~100 s in one call, so
+            # its first 2048 iterations are timed (every stencil launch timed
+            # with HIP events)
+            cols, iters = 32, 2048
+            run = lambda: P.negf_transmission(op, E, n_cols=cols, check=False, tol=TOL,
+                                              col_begin=0, col_count=cols, block_width=cols,
+                                              max_iter=iters, time_matvec=1)
+            (_, d), t = timed(run)
+            x = d.extra
+            emit(row=name, workload=f"wire 64x64x256 R=6 KB, {cols} cols x {E.size} E, "
+                 f"first {iters} iterations", form=f"core B FP64, block {cols}",
+                 seconds=t, column_iterations_per_s=d.total_iters / t,
+                 stencil_us_per_launch=1e6 * x["matvec_seconds"] / max(1, x["matvec_launches"]),
+                 stencil_gb_per_s=x["matvec_bytes"] / max(1e-30, x["matvec_seconds"]) / 1e9)
         elif name == "spectral":
             # the work depends only on the shapes: random eigenpairs of that size
             w = make_custom(16, 16, 80, 0.5, 4, 10, np.linspace(0.1, 1.0, 1024))

@@ -85,6 +85,17 @@ enum {
                              per-energy core only */
 };
 
+/* negf_opts.recover for negf_transmission */
+enum {
+    NEGF_RECOVER_OFF = 0,     /* report what the chosen core reaches */
+    NEGF_RECOVER_RESTART = 1  /* multi-shift items that end in breakdown, at
+                                 max_iter or inaccurate are solved again, each
+                                 as its own seed system, in the FP64
+                                 per-energy core (COCG; items COCG still fails
+                                 then by QMR); their diagnostics are those of
+                                 the re-solve, iters the sum of both runs */
+};
+
 /* negf_opts.direction for negf_transmission */
 enum {
     NEGF_DIR_RL = 0, /* columns on the right CAP support, rows on the left */
@@ -120,11 +131,14 @@ typedef struct {
     int32_t max_iter;    /* Krylov iterations per run; 0 -> 100000 */
     int32_t block_width; /* columns (or items) per block; 0 -> auto */
     int32_t shift_group; /* energies per multi-shift run; 0 -> all */
-    int32_t max_refine;  /* mixed: outer refinement steps; 0 -> 8 */
+    int32_t max_refine;  /* mixed: outer refinement steps, each an FP32 solve
+                            of up to max_iter iterations on the FP64 residual;
+                            0 -> 8 */
     int32_t col_begin;   /* negf_transmission(_grad): first source column of the */
     int32_t col_count;   /* shard to sum over (0 -> all); T is then that shard's
                             partial sum, which shards add up to the full T(E) */
     void* stream;        /* hipStream_t or NULL */
+    int32_t recover;     /* NEGF_RECOVER_* (negf_transmission, multi-shift core) */
 } negf_opts;
 
 /* Optional diagnostics of negf_transmission.  Each array is nullable and is

@@ -13,6 +13,8 @@ from .api import (  # noqa: F401
     NEGF_DIR_RL,
     NEGF_FP64,
     NEGF_MIXED,
+    NEGF_RECOVER_OFF,
+    NEGF_RECOVER_RESTART,
     NEGF_SOLVER_COCG,
     NEGF_SOLVER_QMR,
     Diagnostics,

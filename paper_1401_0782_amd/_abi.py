@@ -21,6 +21,7 @@ NEGF_FP64, NEGF_MIXED = 0, 1
 NEGF_CORE_AUTO, NEGF_CORE_PER_ENERGY, NEGF_CORE_MULTISHIFT = 0, 1, 2
 NEGF_DIR_RL, NEGF_DIR_LR = 0, 1
 NEGF_SOLVER_COCG, NEGF_SOLVER_QMR = 0, 1
+NEGF_RECOVER_OFF, NEGF_RECOVER_RESTART = 0, 1
 
 # every function the header declares
 EXPORTS = (
@@ -57,7 +58,8 @@ class negf_opts(C.Structure):
                 ("direction", C.c_int32),
                 ("tol", C.c_double), ("max_iter", C.c_int32), ("block_width", C.c_int32),
                 ("shift_group", C.c_int32), ("max_refine", C.c_int32), ("col_begin", C.c_int32),
-                ("col_count", C.c_int32), ("stream", C.c_void_p)]
+                ("col_count", C.c_int32), ("stream", C.c_void_p),
+                ("recover", C.c_int32)]
 
 
 class negf_diag(C.Structure):

@@ -15,8 +15,8 @@ import numpy as np
 
 from . import _abi
 from ._abi import (NEGF_CORE_AUTO, NEGF_CORE_MULTISHIFT, NEGF_CORE_PER_ENERGY,  # noqa: F401
-                   NEGF_DIR_LR, NEGF_DIR_RL, NEGF_FP64, NEGF_MIXED, NEGF_SOLVER_COCG,
-                   NEGF_SOLVER_QMR)
+                   NEGF_DIR_LR, NEGF_DIR_RL, NEGF_FP64, NEGF_MIXED, NEGF_RECOVER_OFF,
+                   NEGF_RECOVER_RESTART, NEGF_SOLVER_COCG, NEGF_SOLVER_QMR)
 
 
 class NegfError(RuntimeError):
@@ -119,11 +119,12 @@ def operator_from_wire(wire) -> Operator:
 
 def _opts(precision=NEGF_FP64, core=NEGF_CORE_AUTO, direction=NEGF_DIR_RL, tol=0.0,
           max_iter=0, block_width=0, shift_group=0, max_refine=0, col_begin=0, col_count=0,
-          stream=None, solver=0):
+          stream=None, solver=0, recover=False):
     return _abi.negf_opts(int(precision), int(core), int(solver), int(direction), float(tol),
                           int(max_iter),
                           int(block_width), int(shift_group), int(max_refine), int(col_begin),
-                          int(col_count), C.c_void_p(stream) if stream else None)
+                          int(col_count), C.c_void_p(stream) if stream else None,
+                          NEGF_RECOVER_RESTART if recover else NEGF_RECOVER_OFF)
 
 
 def negf_apply_operator(op: Operator, shifts, x, precision=NEGF_FP64):

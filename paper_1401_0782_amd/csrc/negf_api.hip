@@ -452,7 +452,7 @@ extern "C" negf_status negf_apply_operator(negf_op* op, int32_t precision, int32
 // ---------------------------------------------------------------------------
 struct Defaults {
     int precision, core, solver, direction, max_iter, block_width, shift_group, max_refine;
-    int col_begin, col_count;
+    int col_begin, col_count, recover;
     double tol;
 };
 
@@ -468,6 +468,11 @@ static negf_status read_opts(const negf_opts* o, Defaults* d) {
     d->max_refine = (o && o->max_refine > 0) ? o->max_refine : 8;
     d->col_begin = o ? o->col_begin : 0;
     d->col_count = o ? o->col_count : 0;
+    d->recover = o ? o->recover : NEGF_RECOVER_OFF;
+    if (d->recover != NEGF_RECOVER_OFF && d->recover != NEGF_RECOVER_RESTART) {
+        set_error("unknown recover mode %d", d->recover);
+        return NEGF_E_INVALID_ARG;
+    }
     if (d->col_begin < 0 || d->col_count < 0) {
         set_error("negative column range");
         return NEGF_E_INVALID_ARG;
@@ -1464,7 +1469,11 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
     make_sides(op, d.direction, &sd);
     CHK(restrict_sides(d, &sd));
     const int n_cols = (int)sd.cols.size();
-    const bool want_opt = diag && diag->optical_err;
+    // restarts of failed multi-shift items: the items to restart are those
+    // that end in breakdown or at max_iter, or whose column fails the
+    // optical-theorem check, which is then always computed
+    const bool recover = d.recover == NEGF_RECOVER_RESTART && core == NEGF_CORE_MULTISHIFT;
+    const bool want_opt = (diag && diag->optical_err) || recover;
     const int64_t plane = (int64_t)op->nx * op->ny;
     // the optical check keeps the source side's absorbing rows as well: T
     // weights W_dst on the destination rows and 0 on those, the check's
@@ -1544,22 +1553,21 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
                     }
             }
         }
-    } else {
-        const int wmax = d.block_width ? d.block_width : 64;
-        const int64_t n_items = (int64_t)n_e * n_cols;
-        std::vector<int> icol;
-        std::vector<double> ie, colw;
-        std::vector<int> b_it, b_st;
-        std::vector<double> b_res, b_t;
-        double* d_colw = nullptr;
-        double* d_t = nullptr;
+    }
+    // per-energy solves of the listed items (o = e * n_cols + j), in blocks
+    // of up to wmax items; their diagnostics overwrite those of item o
+    double* d_wfull = nullptr;  // W_L + W_R per grid point, for the optical check
+    auto solve_items = [&](const Defaults& dd, const std::vector<int64_t>& items) -> negf_status {
+        const int wmax = dd.block_width ? dd.block_width : 64;
+        std::vector<int> icol, b_it, b_st, b_rf;
+        std::vector<double> ie, colw, b_res, b_t, b_o;
         // column weights [w], t [w], optical errors [w], source points [w]
+        double* d_colw = nullptr;
         CHK(ws(op, WS_TCOL, (size_t)4 * wmax, &d_colw));
-        d_t = d_colw + wmax;
+        double* d_t = d_colw + wmax;
         double* d_opt = d_t + wmax;
         int* d_jg = reinterpret_cast<int*>(d_opt + wmax);
-        double* d_wfull = nullptr;  // W_L + W_R per grid point, for the optical check
-        if (want_opt) {
+        if (want_opt && !d_wfull) {
             std::vector<double> wf((size_t)op->N);
             for (int64_t i = 0; i < op->N; ++i) {
                 const int z = (int)(i / plane);
@@ -1570,13 +1578,12 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
                                   hipMemcpyHostToDevice, s));
             HIPCHK(hipStreamSynchronize(s));
         }
-        std::vector<double> b_o;
-        std::vector<int> b_rf;
+        const int64_t n_items = (int64_t)items.size();
         for (int64_t i0 = 0; i0 < n_items; i0 += wmax) {
             const int w = (int)std::min<int64_t>(wmax, n_items - i0);
             icol.resize(w); ie.resize(w); colw.resize(w);
             for (int c = 0; c < w; ++c) {
-                const int64_t it = i0 + c;
+                const int64_t it = items[i0 + c];
                 const int e = (int)(it / n_cols), j = (int)(it % n_cols);
                 icol[c] = sd.cols[j];
                 ie[c] = energies[e];
@@ -1589,7 +1596,7 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
             po.h_status = b_st.data();
             po.h_resid = b_res.data();
             po.h_refine = b_rf.data();
-            CHK(run_per_energy(op, d, w, icol.data(), nullptr, ie.data(), po, &total_iters, s, &tm));
+            CHK(run_per_energy(op, dd, w, icol.data(), nullptr, ie.data(), po, &total_iters, s, &tm));
             double2* x64 = (double2*)op->bufs[WS_X64].ptr;
             HIPCHK(hipMemcpyAsync(d_colw, colw.data(), w * sizeof(double), hipMemcpyHostToDevice, s));
             launch_weighted_norm(x64, op->N, w, sd.row0, sd.n_rows, d_roww, d_colw, d_t, s);
@@ -1601,7 +1608,7 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
             }
             HIPCHK(hipStreamSynchronize(s));
             for (int c = 0; c < w; ++c) {
-                const size_t o = (size_t)(i0 + c);  // == e * n_cols + j
+                const size_t o = (size_t)items[i0 + c];
                 tcol[o] = b_t[c];
                 iters[o] = b_it[c];
                 status[o] = b_st[c];
@@ -1610,13 +1617,46 @@ static negf_status transmission_impl(negf_op* op, const negf_opts* opts, int32_t
                 if (want_opt) optical[o] = b_o[c];
             }
         }
+        return NEGF_OK;
+    };
+    if (core != NEGF_CORE_MULTISHIFT) {
+        std::vector<int64_t> all((size_t)n_e * n_cols);
+        for (size_t o = 0; o < all.size(); ++o) all[o] = (int64_t)o;
+        CHK(solve_items(d, all));
     }
     // the optical-theorem check, when computed, must also hold
-    if (want_opt) {
-        const double opt_bar = std::max(1e4 * d.tol, 1e-8);
+    const double opt_bar = std::max(1e4 * d.tol, 1e-8);
+    auto flag_optical = [&]() {
+        if (!want_opt) return;
         for (size_t o = 0; o < status.size(); ++o)
             if (status[o] == NEGF_ITEM_CONVERGED && !(optical[o] <= opt_bar))
                 status[o] = NEGF_ITEM_INACCURATE;
+    };
+    flag_optical();
+    if (recover) {
+        // each failed item is restarted as its own seed system (a breakdown of
+        // the shared seed ends every shift of the column at once, and the
+        // shifted residuals of a restart would no longer be collinear): FP64
+        // per-energy COCG with true-residual refinement, then QMR for those
+        // COCG still fails
+        std::vector<int> spent(iters.size(), 0);  // iterations of the earlier runs
+        std::vector<int64_t> redo;
+        Defaults d2 = d;
+        d2.precision = NEGF_FP64;
+        d2.core = NEGF_CORE_PER_ENERGY;
+        for (int pass = 0; pass < 2; ++pass) {
+            redo.clear();
+            for (size_t o = 0; o < status.size(); ++o)
+                if (status[o] != NEGF_ITEM_CONVERGED) {
+                    redo.push_back((int64_t)o);
+                    spent[o] += iters[o];
+                }
+            if (redo.empty()) break;
+            d2.solver = pass == 0 ? NEGF_SOLVER_COCG : NEGF_SOLVER_QMR;
+            CHK(solve_items(d2, redo));
+            flag_optical();
+        }
+        for (size_t o = 0; o < iters.size(); ++o) iters[o] += spent[o];
     }
     int n_bad = 0, n_break = 0;
     for (int e = 0; e < n_e; ++e) {
@@ -2302,11 +2342,12 @@ struct BatchJob {
 };
 
 // Whether junction i of the batch runs as one resumable multi-shift run (FP64
-// multi-shift core, every energy in one shift group, streamed columns); the
-// others go through negf_transmission's own driver, one at a time.
+// multi-shift core, every energy in one shift group, streamed columns, no
+// restarts); the others go through negf_transmission's own driver, one at a
+// time.
 static bool batch_interleaves(const Defaults& d) {
     return pick_core(d) == NEGF_CORE_MULTISHIFT && d.precision == NEGF_FP64 &&
-           d.shift_group == 0 && !column_stream_disabled();
+           d.shift_group == 0 && !column_stream_disabled() && d.recover == NEGF_RECOVER_OFF;
 }
 
 static negf_status batch_job_start(BatchJob* job, const negf_opts* opts, const double* energies) {

@@ -465,6 +465,21 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
             }
             q[2 * RAD] = lead;
         }
+        // y-halo rows of plane z (recomputed from r and p_{k-1}), issued
+        // before the next plane's prefetch: vector loads return in order, so
+        // waiting for these does not wait for the prefetch behind them
+        if (has_halo) {
+            for (int k = tid; k < 2 * RAD * nx; k += NT) {
+                const int hr = k / nx, hx = k % nx;
+                const int yy = hr < RAD ? (hr - RAD) : (rows + hr - RAD);
+                const int gy = y0 + yy;
+                cplx_t<R> val;
+                val.x = 0;
+                val.y = 0;
+                if (gy >= 0 && gy < ny) val = p_at((int64_t)z * plane + (int64_t)gy * nx + hx);
+                tile[(yy + RAD) * pitch + RAD + hx] = val;
+            }
+        }
         // prefetch plane z + RAD + 1 and V of plane z + 1
         {
             const int zl = z + RAD + 1;
@@ -484,18 +499,6 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
         if (own) {
             tile[(ly + RAD) * pitch + RAD + lx] = q[RAD];
             if (FUSED) pout[co + (int64_t)z * plane + col_off] = q[RAD];
-        }
-        if (has_halo) {
-            for (int k = tid; k < 2 * RAD * nx; k += NT) {
-                const int hr = k / nx, hx = k % nx;
-                const int yy = hr < RAD ? (hr - RAD) : (rows + hr - RAD);
-                const int gy = y0 + yy;
-                cplx_t<R> val;
-                val.x = 0;
-                val.y = 0;
-                if (gy >= 0 && gy < ny) val = p_at((int64_t)z * plane + (int64_t)gy * nx + hx);
-                tile[(yy + RAD) * pitch + RAD + hx] = val;
-            }
         }
         __syncthreads();
         if (own) {

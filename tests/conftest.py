@@ -23,3 +23,12 @@ def gpu_lib():
     from paper_1401_0782_amd import _abi
 
     return _abi.load()
+
+
+@pytest.fixture(autouse=True)
+def _gpu_runtime_first(request):
+    """Every GPU test brings up torch's GPU runtime before the library's first
+    call (a test selected on its own, without gpu_lib, would otherwise let the
+    library initialise HIP first, after which torch reports no GPU)."""
+    if request.node.get_closest_marker("gpu"):
+        request.getfixturevalue("gpu_lib")

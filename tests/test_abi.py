@@ -212,3 +212,17 @@ def test_planes_whose_stencil_tile_overflows_lds_rejected(nx, ny, ok):
         _build(**kw)
     except NegfError as e:
         assert "stencil tile" not in str(e) and "widest x-row" not in str(e)
+
+
+def test_enum_constants_match_header():
+    """Every enumerator of include/negf.h has the same value in the binding."""
+    from paper_1401_0782_amd import _abi
+
+    text = re.sub(r"/\*.*?\*/", "", (ROOT / "include" / "negf.h").read_text(), flags=re.S)
+    found = {}
+    for body in re.findall(r"enum\s*\{(.*?)\}", text, re.S):
+        for name, val in re.findall(r"\b(NEGF_[A-Z0-9_]+)\s*=\s*(\d+)", body):
+            found[name] = int(val)
+    assert len(found) >= 21
+    for name, val in found.items():
+        assert getattr(_abi, name) == val, name

@@ -1,5 +1,5 @@
 """Host logic of bench.py that needs no GPU: the counter summary is used only
-for the stencil source, kernel and launch shape it was taken on, and runs on
+for the kernel source, kernel and launch shape it was taken on, and runs on
 more than one GPU are refused."""
 
 import pathlib
@@ -26,12 +26,9 @@ def _fields():
 
 
 def test_committed_counters_are_used_only_for_their_source():
-    import hashlib
-
     f = _fields()
     ratio, why = bench._traffic_from_profile(KERNEL, (192, 1))
-    src = hashlib.sha256(bench.KERNEL_SRC.read_bytes()).hexdigest()[:16]
-    if f["stencil_src_sha256_16"] != src:
+    if f["kernel_src_sha256_16"] != bench.kernel_source_hash(KERNEL):
         # the source changed after the counters were taken: no traffic figure
         assert ratio is None and "predate" in why
         return
@@ -42,19 +39,31 @@ def test_committed_counters_are_used_only_for_their_source():
     assert 1.0 <= ratio < 1.3
 
 
+STAND_IN = """// stand-in source
+template <int RAD, typename R, bool FUSED>
+__global__ void k_cocg_plane(const R* r) {
+    body();
+}
+
+template <int RAD, typename R>
+FusedGeom fused_geom(const negf_op* op, int w) {
+    return FusedGeom{};
+}
+"""
+
+
 @pytest.fixture
 def matched(monkeypatch, tmp_path):
-    """The committed counter summary, re-keyed to a stand-in stencil source so
+    """The committed counter summary, re-keyed to a stand-in kernel source so
     that the checks below hold whatever the source is now."""
-    import hashlib
-
     src = tmp_path / "stencil.hip"
-    src.write_text("// stand-in source\n")
-    old_hash = _fields()["stencil_src_sha256_16"]
-    counters = tmp_path / "counters.txt"
-    counters.write_text(bench.COUNTERS.read_text().replace(
-        old_hash, hashlib.sha256(src.read_bytes()).hexdigest()[:16]))
+    src.write_text(STAND_IN)
     monkeypatch.setattr(bench, "KERNEL_SRC", src)
+    monkeypatch.setattr(bench, "KERNEL_HELPERS", tmp_path / "none.h")
+    old_hash = _fields()["kernel_src_sha256_16"]
+    counters = tmp_path / "counters.txt"
+    counters.write_text(bench.COUNTERS.read_text().replace(old_hash,
+                                                           bench.kernel_source_hash(KERNEL)))
     monkeypatch.setattr(bench, "COUNTERS", counters)
     return src
 
@@ -75,7 +84,16 @@ def test_ratio_follows_the_tuned_shape(matched):
 def test_other_kernel_or_source_gives_no_traffic(matched):
     r, why = bench._traffic_from_profile("k_cocg_apply<6,double,1024,true>", (192, 1))
     assert r is None and "k_cocg_plane" in why
-    matched.write_text(matched.read_text() + "// changed\n")
+    # edits outside the kernel, its geometry and its helpers keep the figure
+    matched.write_text(matched.read_text() + "// changed elsewhere\nvoid other() {\n}\n")
+    r, why = bench._traffic_from_profile(KERNEL, (192, 1))
+    assert why is None and r is not None
+    # an edit of the kernel drops it
+    matched.write_text(matched.read_text().replace("body();", "body(); more();"))
+    r, why = bench._traffic_from_profile(KERNEL, (192, 1))
+    assert r is None and "predate" in why
+    # so does an edit of the launch geometry
+    matched.write_text(STAND_IN.replace("return FusedGeom{};", "return FusedGeom{1};"))
     r, why = bench._traffic_from_profile(KERNEL, (192, 1))
     assert r is None and "predate" in why
 

@@ -86,7 +86,7 @@ def test_oracle_samples(op2, wire2):
             assert err <= 6e-13, (smp, t)
 
 
-def test_largest_wire_optical_theorem():
+def test_largest_wire_optical_theorem(gpu_lib):
     """The 64x64x256 R=6 wire with 80 atoms' projectors (N = 1,048,576, the
     largest workload), 8 source columns x 16 energies (energies[::64]) through
     the multi-shift core: the per-column optical theorem on the CAP rows."""

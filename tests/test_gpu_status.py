@@ -8,6 +8,8 @@
   optical-theorem check requested, every item the library reports converged
   matches the oracle, every other one is flagged, and the call then does not
   return NEGF_OK;
+* with restarts requested, the multi-shift items that failed are solved again
+  in the per-energy core and every item of the chain converges;
 * the per-item optical-theorem error and refinement steps of negf_diag;
 * the gap between the multi-shift core's residual estimate (its stopping
   rule) and the FP64 true residual ||b - A x|| / ||b|| on the 32x32x192 wire.
@@ -94,6 +96,48 @@ def test_hostile_chain_flags_what_it_does_not_solve(gpu_lib, hostile_chain, core
     else:
         assert d.status in (_abi.NEGF_E_BREAKDOWN, _abi.NEGF_E_NOT_CONVERGED)
         assert d.n_not_converged == int((~ok).sum())
+
+
+def test_hostile_chain_restarts_recover_every_item(gpu_lib, hostile_chain):
+    """With NEGF_RECOVER_RESTART the multi-shift items the chain breaks down,
+    leaves at max_iter or fails the optical check on are solved again, each
+    as its own seed, in the FP64 per-energy core: every item then converges
+    and matches the oracle, and T is returned with NEGF_OK.  The restarted
+    items are those with refinement steps (the multi-shift core does none)."""
+    import paper_1401_0782_amd as P
+    from paper_1401_0782_amd import _abi
+
+    w, cols, t_ref = hostile_chain
+    op = P.operator_from_wire(w)
+    T0, d0 = P.negf_transmission(op, w.energies, n_cols=len(cols), check=False, tol=1e-12,
+                                 max_iter=20000, optical=True, core=P.NEGF_CORE_MULTISHIFT)
+    failed = d0.item_status != _abi.NEGF_ITEM_CONVERGED
+    T, d = P.negf_transmission(op, w.energies, n_cols=len(cols), tol=1e-12, max_iter=20000,
+                               optical=True, core=P.NEGF_CORE_MULTISHIFT, recover=True)
+    restarted = d.refine_steps > 0
+    print(f"{int(failed.sum())} of {failed.size} items failed in the multi-shift core; "
+          f"{int(restarted.sum())} restarted")
+    assert d.status == _abi.NEGF_OK and d.n_not_converged == 0
+    assert np.all(d.item_status == _abi.NEGF_ITEM_CONVERGED)
+    assert np.array_equal(restarted, failed)
+    assert np.max(np.abs(d.t_col - t_ref)) <= 1e-8
+    assert np.max(np.abs(T - t_ref.sum(axis=1))) <= 1e-8
+    assert d.optical_err.max() <= 1e-8
+    # the items that did not fail are the multi-shift core's own, unchanged
+    assert np.array_equal(d.t_col[~failed], d0.t_col[~failed])
+    assert np.all(d.iters[failed] > d0.iters[failed])
+
+
+def test_restart_needs_no_optical_request(gpu_lib, hostile_chain):
+    """The restart mode runs the optical check itself: without the optical
+    diagnostics requested, T is the same as with them."""
+    import paper_1401_0782_amd as P
+
+    w, cols, t_ref = hostile_chain
+    op = P.operator_from_wire(w)
+    T = P.negf_transmission(op, w.energies, tol=1e-12, max_iter=20000,
+                            core=P.NEGF_CORE_MULTISHIFT, recover=True)
+    assert np.max(np.abs(T - t_ref.sum(axis=1))) <= 1e-8
 
 
 @pytest.mark.parametrize("core,prec", FORMS)
