@@ -216,6 +216,49 @@ FP64_PEAK_TFS = 78.6
 ROWS = ("small", "mixed", "batch", "full", "adjoint", "large", "spectral", "current", "copy")
 
 
+def precision_forms(P, op, wire, n_cols=4, n_e=4):
+    """The metric's comparison, after the timed region and outside it: a
+    sample of the same wire (n_cols source columns spread over the right
+    absorbing region x n_e energies spread over the grid) in the mixed form
+    (FP32 Krylov vectors and matvec, FP64 scalars, true residual and
+    refinement; per-energy core), FP64 in the same core, and FP64 in the
+    multi-shift core the headline line uses, each timed whole on the host
+    clock after the same call has run once.  solves/s, |dT| against the
+    multi-shift core, and which form is fastest at |dT| <= 1e-6."""
+    import numpy as np
+    import torch
+
+    from workloads import rhs_columns
+
+    n_src = len(rhs_columns(wire))
+    E = wire.energies[np.linspace(0, wire.energies.size - 1, n_e).astype(int)]
+    cols = np.linspace(0, n_src - 1, n_cols).astype(int)
+    forms = [("FP64 multi-shift (core B)", dict(core=P.NEGF_CORE_MULTISHIFT, block_width=1)),
+             ("FP64 per-energy (core A)", dict(core=P.NEGF_CORE_PER_ENERGY)),
+             ("mixed per-energy (core A)", dict(precision=P.NEGF_MIXED))]
+    res = {}
+    for name, kw in forms:
+        def run(**extra):
+            return sum(P.negf_transmission(op, E, tol=TOL, col_begin=int(c), col_count=1,
+                                           **kw, **extra) for c in cols)
+        run(max_iter=32, check=False)  # warm-up: workspace, graphs
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        T = run()
+        torch.cuda.synchronize()
+        res[name] = (T, time.perf_counter() - t)
+        print(f"precision form {name}: {res[name][1]:.2f} s", file=sys.stderr, flush=True)
+    T0 = res[forms[0][0]][0]
+    out = {"sample": f"{n_cols} source columns (spread over the right absorbing region) x "
+                     f"{n_e} energies, tol {TOL:g}, one column per call"}
+    for name, (T, t) in res.items():
+        out[name] = {"solves_per_s": n_cols * n_e / t,
+                     "max_abs_dT_vs_multishift": float(np.abs(T - T0).max())}
+    ok = [n for n in res if out[n]["max_abs_dT_vs_multishift"] <= 1e-6]
+    out["fastest_at_dT_1e-6"] = max(ok, key=lambda n: out[n]["solves_per_s"])
+    return out
+
+
 def measure_rows(names):
     """Secondary measurements (one JSON line each): the other workloads and
     forms of the path, timed whole on the host clock around synchronised
@@ -412,6 +455,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=60000)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-forms", action="store_true",
+                    help="skip the mixed / FP64 comparison on a sample after the timed steps")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--launch-shape", type=str, default=None, metavar="WG_TARGET,PLANE",
@@ -570,6 +615,8 @@ def main():
         },
         "roofline": roofline,
     }
+    if not args.no_precision_forms:
+        out["precision_forms"] = precision_forms(P, op, wire)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -308,6 +308,25 @@ typedef struct {
 negf_status negf_tune(negf_op* op, const negf_opts* opts, int32_t n_e, const double* energies,
                       int32_t probe_iters, negf_tune_result* result);
 
+/* negf_tune with an on-disk cache of its choice.  The key is the operator's
+ * shape and the tuning request: grid (nx, ny, nz), stencil radius, projector
+ * count, source columns and kept rows of opts->direction, energies per shift
+ * group, opts->block_width, probe_iters, and the device (architecture name
+ * and compute-unit count).  A key found in cache_path sets the stored shape
+ * without any probe (result->n_tried = 0, result->us_per_column_iteration[0]
+ * the stored timing); otherwise negf_tune runs and one line is appended to
+ * the file (created if missing).  The file is plain text, one
+ * "key => block_width wg_target plane_kernel us" line per entry; the last
+ * line for a key wins, and lines that do not parse are skipped.  Entries of
+ * an older library version are not used (the version is part of the key).
+ *   cache_path  a file path; NEGF_E_INVALID_ARG if null or empty.  File
+ *               errors are not failures: a missing or unreadable cache
+ *               reads as empty, and a choice that cannot be appended is
+ *               still set on the operator and returned. */
+negf_status negf_tune_cached(negf_op* op, const negf_opts* opts, int32_t n_e,
+                             const double* energies, int32_t probe_iters,
+                             const char* cache_path, negf_tune_result* result);
+
 /* Sets the launch shape negf_tune would keep, e.g. one cached from an earlier
  * process: block_width 0 and wg_target 0 restore the built-in defaults (64
  * columns; 256 stencil work-groups per launch), plane_kernel -1 the automatic

@@ -32,6 +32,7 @@ EXPORTS = (
     "negf_transmission",
     "negf_transmission_batch",
     "negf_tune",
+    "negf_tune_cached",
     "negf_set_launch_shape",
     "negf_current",
     "negf_spectral_transmission",
@@ -112,6 +113,8 @@ def load(path: str | None = None):
                                             vp, C.POINTER(vp), C.POINTER(vp), vp, C.c_int32]
     lib.negf_tune.argtypes = [vp, C.POINTER(negf_opts), C.c_int32, vp, C.c_int32,
                               C.POINTER(negf_tune_result)]
+    lib.negf_tune_cached.argtypes = [vp, C.POINTER(negf_opts), C.c_int32, vp, C.c_int32,
+                                     C.c_char_p, C.POINTER(negf_tune_result)]
     lib.negf_set_launch_shape.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
     lib.negf_spectral_transmission.argtypes = [vp, C.c_int32, vp, vp, C.c_double, C.c_int32, vp,
                                                vp]

@@ -241,15 +241,23 @@ def negf_transmission_grad(op: Operator, energies, weights, dL_dV=None, want_T=T
     return dL_dV, T
 
 
-def negf_tune(op: Operator, energies, probe_iters: int = 0, **opts) -> dict:
+def negf_tune(op: Operator, energies, probe_iters: int = 0, cache: Optional[str] = None,
+              **opts) -> dict:
     """Autotune the multi-shift launch shape of op (block width, stencil
     z-chunking, stencil kernel) by timing short probe runs; later calls with
-    block_width=0 use the choice.  Returns the choice and the timing table."""
+    block_width=0 use the choice.  With cache (a file path) a choice stored
+    there for the same operator shape, request and device is used without
+    probes (an empty "tried" table), and a new one is appended.  Returns the
+    choice and the timing table."""
     e = np.ascontiguousarray(energies, dtype=np.float64)
     o = _opts(**opts)
     res = _abi.negf_tune_result()
-    _check(_lib().negf_tune(op.handle, C.byref(o), e.size, _ptr(e), int(probe_iters),
-                            C.byref(res)))
+    if cache is not None:
+        _check(_lib().negf_tune_cached(op.handle, C.byref(o), e.size, _ptr(e), int(probe_iters),
+                                       str(cache).encode(), C.byref(res)))
+    else:
+        _check(_lib().negf_tune(op.handle, C.byref(o), e.size, _ptr(e), int(probe_iters),
+                                C.byref(res)))
     n = res.n_tried
     return {
         "block_width": res.block_width,

@@ -2126,6 +2126,94 @@ extern "C" negf_status negf_tune(negf_op* op, const negf_opts* opts, int32_t n_e
     return tune_impl(op, opts, n_e, energies, probe_iters, result);
 }
 
+// the cache key of a tuning request (no " => " inside: that separates the value)
+static std::string tune_key(const negf_op* op, const Defaults& d, int n_e, int probe_iters) {
+    Sides sd;
+    make_sides(op, d.direction, &sd);
+    const int ng = d.shift_group ? std::min(d.shift_group, n_e) : n_e;
+    hipDeviceProp_t prop;
+    std::memset(&prop, 0, sizeof prop);
+    (void)hipGetDeviceProperties(&prop, op->device);
+    char buf[640];
+    std::snprintf(buf, sizeof buf,
+                  "%s|%s|cu%d|grid%dx%dx%d|R%d|proj%d|cols%zu|rows%d|ng%d|bw%d|probe%d",
+                  negf_version(), prop.gcnArchName, prop.multiProcessorCount, op->nx, op->ny,
+                  op->nz, op->R, op->kb.n_proj, sd.cols.size(), sd.n_rows, ng, d.block_width,
+                  probe_iters);
+    return buf;
+}
+
+extern "C" negf_status negf_tune_cached(negf_op* op, const negf_opts* opts, int32_t n_e,
+                                        const double* energies, int32_t probe_iters,
+                                        const char* cache_path, negf_tune_result* result) {
+    (void)hipGetLastError();  // a stale error of an earlier call must not fail this one
+    if (!op) {
+        set_error("null op");
+        return NEGF_E_INVALID_ARG;
+    }
+    if (!cache_path || !cache_path[0]) {
+        set_error("null or empty cache path");
+        return NEGF_E_INVALID_ARG;
+    }
+    Defaults d;
+    CHK(read_opts(opts, &d));
+    CHK(check_energies(n_e, energies));
+    if (probe_iters < 0) {
+        set_error("probe_iters must be >= 0");
+        return NEGF_E_INVALID_ARG;
+    }
+    const std::string key = tune_key(op, d, n_e, probe_iters);
+    int bw = 0, tg = 0, pk = 0;
+    double us = 0.0;
+    bool hit = false;
+    if (FILE* f = std::fopen(cache_path, "r")) {
+        char line[1024];
+        while (std::fgets(line, sizeof line, f)) {
+            const char* sep = std::strstr(line, " => ");
+            if (!sep || (size_t)(sep - line) != key.size() ||
+                std::strncmp(line, key.c_str(), key.size()) != 0)
+                continue;
+            int a = 0, b = 0, c = 0;
+            double u = 0.0;
+            if (std::sscanf(sep + 4, "%d %d %d %lf", &a, &b, &c, &u) == 4 && a > 0 && b > 0 &&
+                (c == 0 || c == 1)) {
+                bw = a;
+                tg = b;
+                pk = c;
+                us = u;
+                hit = true;  // the last line for the key wins
+            }
+        }
+        std::fclose(f);
+    }
+    if (hit) {
+        CHK(negf_set_launch_shape(op, bw, tg, pk));
+        if (result) {
+            std::memset(result, 0, sizeof *result);
+            result->block_width = bw;
+            result->wg_target = tg;
+            result->plane_kernel = pk;
+            result->n_tried = 0;
+            result->us_per_column_iteration[0] = us;
+        }
+        return NEGF_OK;
+    }
+    negf_tune_result local;
+    negf_tune_result* r = result ? result : &local;
+    CHK(tune_impl(op, opts, n_e, energies, probe_iters, r));
+    double best = 0.0;
+    for (int i = 0; i < r->n_tried; ++i)
+        if (r->tried_block_width[i] == r->block_width && r->tried_wg_target[i] == r->wg_target &&
+            r->tried_plane_kernel[i] == r->plane_kernel)
+            best = r->us_per_column_iteration[i];
+    if (FILE* f = std::fopen(cache_path, "a")) {
+        std::fprintf(f, "%s => %d %d %d %.6g\n", key.c_str(), r->block_width, r->wg_target,
+                     r->plane_kernel, best);
+        std::fclose(f);
+    }
+    return NEGF_OK;
+}
+
 void launch_landauer(const double* e, const double* t, int n_e, const double* bias, int n_bias,
                      double e_fermi, double kt, double* out, hipStream_t s);
 

@@ -31,6 +31,43 @@ def test_tune_picks_fastest_candidate_and_keeps_results(gpu_lib):
     assert np.max(np.abs(T_tuned - T_ref)) <= 1e-8
 
 
+def test_tune_cache_round_trip(gpu_lib, tmp_path):
+    """negf_tune_cached: the first call tunes and appends one line to the
+    cache; a second operator of the same shape then gets the same choice from
+    the file without probes (n_tried = 0, the stored timing), and its T is
+    the oracle's; another request (a fixed block width) is a new key; a line
+    that does not parse is skipped."""
+    import paper_1401_0782_amd as P
+
+    wire = make_wire(1)
+    cache = tmp_path / "tune.txt"
+    cache.write_text("garbage without separator\n")
+    op = P.operator_from_wire(wire)
+    first = P.negf_tune(op, wire.energies, cache=str(cache))
+    assert len(first["tried"]) == 50
+    lines = [ln for ln in cache.read_text().splitlines() if " => " in ln]
+    assert len(lines) == 1 and "grid8x8x32" in lines[0] and "|R2|" in lines[0]
+    op2 = P.operator_from_wire(wire)
+    second = P.negf_tune(op2, wire.energies, cache=str(cache))
+    assert second["tried"] == []
+    key = ("block_width", "wg_target", "plane_kernel")
+    assert tuple(second[k] for k in key) == tuple(first[k] for k in key)
+    T = P.negf_transmission(op2, wire.energies, tol=1e-12)
+    assert np.max(np.abs(T - O.transmission(wire, method="dense"))) <= 1e-8
+    third = P.negf_tune(op2, wire.energies, cache=str(cache), block_width=32)
+    assert {t[0] for t in third["tried"]} == {32}
+    assert len([ln for ln in cache.read_text().splitlines() if " => " in ln]) == 2
+
+
+def test_tune_cache_rejects_empty_path(gpu_lib):
+    import paper_1401_0782_amd as P
+
+    wire = make_wire(1)
+    op = P.operator_from_wire(wire)
+    with pytest.raises(P.NegfError, match="cache path"):
+        P.negf_tune(op, wire.energies, cache="")
+
+
 @pytest.mark.parametrize("plane", [0, 1])
 def test_every_tuned_shape_matches_oracle(gpu_lib, plane):
     """A fixed block width tunes only z-chunking and kernel; each probe shape,
