@@ -59,6 +59,9 @@ def _function_text(src, name):
     return src[m.start(): end + 3 if end >= 0 else len(src)]
 
 
+GEOMETRY = {"k_cocg_plane": "plane_geom", "k_cocg_apply": "rowtile_geom"}
+
+
 def kernel_source_hash(kernel):
     """16 hex digits of sha256 over the source the counters depend on: the
     stencil kernel's own function, the function that sets its launch geometry
@@ -66,7 +69,7 @@ def kernel_source_hash(kernel):
     source (the other kernel, comments) leave it unchanged."""
     name = kernel.split("<", 1)[0]
     src = KERNEL_SRC.read_text()
-    parts = [_function_text(src, name), _function_text(src, "fused_geom")]
+    parts = [_function_text(src, name), _function_text(src, GEOMETRY.get(name, "fused_geom"))]
     if KERNEL_HELPERS.exists():
         helpers = KERNEL_HELPERS.read_text()
         parts += [_function_text(helpers, "ld_once"), _function_text(helpers, "st_once")]

@@ -98,6 +98,13 @@ def load(path: str | None = None):
         raise RuntimeError(
             f"libnegf is not built ({p} missing); run __graft_entry__.build() "
             "or python paper_1401_0782_amd/build.py")
+    # torch's ROCm wheel carries its own HIP and HSA runtimes.  In a process
+    # that also uses torch they must be loaded before this library: loaded
+    # after it, one of the two sides finds no GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(str(p))
     vp = C.c_void_p
     lib.negf_build_operator.argtypes = [C.POINTER(negf_grid), C.c_int32, vp, C.POINTER(negf_kb),

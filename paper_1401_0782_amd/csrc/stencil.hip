@@ -364,7 +364,7 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
     cplx_t<R>* __restrict__ y, int nx, int ny, int nz, int ty, int n_ytiles, int zchunk,
     Coef<R> cf, double a0, const double* __restrict__ v, const double* __restrict__ wz,
     const double* __restrict__ shift, const int* __restrict__ skip, const int* __restrict__ kit,
-    const double2* __restrict__ beta, double2* __restrict__ part, int xcd_group) {
+    const double2* __restrict__ beta, double2* __restrict__ part, int xcd_group, int nt_store) {
     extern __shared__ unsigned char smem_raw[];
     // launch index -> (tile, column).  The y-tiles of one z-chunk read each
     // other's boundary rows as halo at the same plane and time; with
@@ -498,7 +498,12 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
         // stage the centre plane
         if (own) {
             tile[(ly + RAD) * pitch + RAD + lx] = q[RAD];
-            if (FUSED) pout[co + (int64_t)z * plane + col_off] = q[RAD];
+            if (FUSED) {
+                if (nt_store)
+                    st_once<R>(pout + co + (int64_t)z * plane + col_off, q[RAD]);
+                else
+                    pout[co + (int64_t)z * plane + col_off] = q[RAD];
+            }
         }
         __syncthreads();
         if (own) {
@@ -520,7 +525,10 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
             cplx_t<R> o;
             o.x = ax;
             o.y = ay;
-            y[co + gi] = o;
+            if (nt_store)
+                st_once<R>(y + co + gi, o);
+            else
+                y[co + gi] = o;
             if (FUSED) {
                 dot_x += (double)xi.x * ax - (double)xi.y * ay;
                 dot_y += (double)xi.x * ay + (double)xi.y * ax;
@@ -724,32 +732,41 @@ struct FusedGeom {
     size_t lds;
 };
 
+// whole-plane kernel: one plane per work-group, z-chunks for every CU
 template <int RAD, typename R>
-FusedGeom fused_geom(const negf_op* op, int w) {
+FusedGeom plane_geom(const negf_op* op, int w) {
     FusedGeom g;
     const int nx = op->nx, ny = op->ny, nz = op->nz;
     const int pts = nx * ny;
-    g.whole_plane = pts <= 1024 && op->plane_kernel != 0 &&
-                    getenv("NEGF_NO_PLANE_KERNEL") == nullptr;
-    if (g.whole_plane) {
-        g.nt = (pts + 63) / 64 * 64;
-        g.ty = ny;
-        g.n_ytiles = 1;
-        // z-chunks: enough work-groups for every CU, each a multiple of the
-        // 2R+1 unrolled steps (the last trip of a chunk runs whole)
-        constexpr int Q = 2 * RAD + 1;
-        const int target = op->wg_target > 0 ? op->wg_target : 256;
-        int nzc = std::max(1, (target + w - 1) / w);
-        int zc = (nz + nzc - 1) / nzc;
-        zc = std::max(Q, ((zc + Q - 1) / Q) * Q);
-        g.zchunk = zc;
-        g.n_z = (nz + zc - 1) / zc;
-        g.lds = 2 * (size_t)(nx + 2 * RAD) * (ny + 2 * RAD) * sizeof(cplx_t<R>);
-        return g;
-    }
+    g.whole_plane = true;
+    g.nt = (pts + 63) / 64 * 64;
+    g.ty = ny;
+    g.n_ytiles = 1;
+    // z-chunks: enough work-groups for every CU, each a multiple of the
+    // 2R+1 unrolled steps (the last trip of a chunk runs whole)
+    constexpr int Q = 2 * RAD + 1;
+    const int target = op->wg_target > 0 ? op->wg_target : 256;
+    int nzc = std::max(1, (target + w - 1) / w);
+    int zc = (nz + nzc - 1) / nzc;
+    zc = std::max(Q, ((zc + Q - 1) / Q) * Q);
+    g.zchunk = zc;
+    g.n_z = (nz + zc - 1) / zc;
+    g.lds = 2 * (size_t)(nx + 2 * RAD) * (ny + 2 * RAD) * sizeof(cplx_t<R>);
+    return g;
+}
+
+// row-tiled kernel: y-tiles of whole x-rows, z-chunks for every CU
+template <int RAD, typename R>
+FusedGeom rowtile_geom(const negf_op* op, int w) {
+    FusedGeom g;
+    const int nx = op->nx, ny = op->ny, nz = op->nz;
+    g.whole_plane = false;
     g.nt = (nx * ny <= 256) ? 256 : 1024;
-    g.ty = std::min(ny, g.nt / nx);
-    g.n_ytiles = (ny + g.ty - 1) / g.ty;
+    // as few y-tiles as the block's rows allow, with the rows spread evenly
+    // over them (34 rows of 34 points: 17 + 17, not 30 + 4)
+    const int rows_max = std::min(ny, g.nt / nx);
+    g.n_ytiles = (ny + rows_max - 1) / rows_max;
+    g.ty = (ny + g.n_ytiles - 1) / g.n_ytiles;
     // enough work-groups to give every CU work; each z-chunk re-reads 2R planes
     const long target = op->wg_target > 0 ? op->wg_target : ((g.nt == 1024) ? 256 : 1024);
     int zc = nz;
@@ -758,6 +775,13 @@ FusedGeom fused_geom(const negf_op* op, int w) {
     g.n_z = (nz + zc - 1) / zc;
     g.lds = 2 * (size_t)(nx + 2 * RAD) * (g.ty + 2 * RAD) * sizeof(cplx_t<R>);
     return g;
+}
+
+template <int RAD, typename R>
+FusedGeom fused_geom(const negf_op* op, int w) {
+    const bool whole_plane = op->nx * op->ny <= 1024 && op->plane_kernel != 0 &&
+                             getenv("NEGF_NO_PLANE_KERNEL") == nullptr;
+    return whole_plane ? plane_geom<RAD, R>(op, w) : rowtile_geom<RAD, R>(op, w);
 }
 
 // gfx950 has 160 KB of LDS per CU; dynamic allocations above 64 KB must be
@@ -796,11 +820,18 @@ void fused_launch(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin, c
         const char* e = getenv("NEGF_ROWTILE_XCD");
         return (e && e[0] == '0') ? 0 : 1;
     }();
+    // p_k and q stored with the non-temporal hint only when one block of
+    // them outgrows the last-level cache: on the 64x64x256 wire (537 MB per
+    // 32-column vector) the hint gained 4 %, on the junction batch (at most
+    // 262 MB per 64-column vector) it cost 4 %, where q still comes from the
+    // cache for the update kernel that reads it next
+    const int nt_store = (double)w * (double)op->N * sizeof(cplx_t<R>) > 384.0 * (1 << 20);
     auto go = [&](auto kern, int nt) {
         if (g.lds > 65536) allow_large_lds((const void*)kern);
         hipLaunchKernelGGL(kern, grid, dim3(nt), g.lds, s, r, pin, pout, y, op->nx, op->ny,
                            op->nz, g.ty, g.n_ytiles, g.zchunk, cf, op->coef.a[0], op->d_v,
-                           op->d_wz, shift, skip, kit, beta, part, g.n_ytiles > 1 ? xcd_group : 0);
+                           op->d_wz, shift, skip, kit, beta, part, g.n_ytiles > 1 ? xcd_group : 0,
+                           nt_store);
     };
     if (g.nt == 256)
         go(k_cocg_apply<RAD, R, 256, FUSED>, 256);

@@ -46,7 +46,7 @@ __global__ void k_cocg_plane(const R* r) {
 }
 
 template <int RAD, typename R>
-FusedGeom fused_geom(const negf_op* op, int w) {
+FusedGeom plane_geom(const negf_op* op, int w) {
     return FusedGeom{};
 }
 """
