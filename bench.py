@@ -45,7 +45,7 @@ KERNEL_SRC = ROOT / "paper_1401_0782_amd" / "csrc" / "stencil.hip"
 KERNEL_HELPERS = ROOT / "paper_1401_0782_amd" / "csrc" / "negf_internal.h"
 
 
-KERNELS = {1: "k_cocg_plane<6,double,true>", 0: "k_cocg_apply<6,double,1024,true>"}
+KERNELS = {1: "k_cocg_plane<6,double,true,true>", 0: "k_cocg_apply<6,double,1024,true>"}
 
 
 def _function_text(src, name):

@@ -574,7 +574,7 @@ __global__ __launch_bounds__(NT) void k_cocg_apply(
 //  * the z-queue is unrolled 2R+1 ways: slot (u + d) mod (2R+1) holds plane
 //    z + d - R at unrolled step u, so no register is rewritten while a store
 //    that reads it may still be pending.
-template <int RAD, typename R, bool FUSED>
+template <int RAD, typename R, bool FUSED, bool NTH>
 __global__ __launch_bounds__(1024) void k_cocg_plane(
     const cplx_t<R>* __restrict__ r, const cplx_t<R>* __restrict__ pin, cplx_t<R>* __restrict__ pout,
     cplx_t<R>* __restrict__ y, cplx_t<R>* __restrict__ sink, int nx, int ny, int nz, int zchunk,
@@ -621,7 +621,11 @@ __global__ __launch_bounds__(1024) void k_cocg_plane(
         const int zc = min(max(zz, 0), nz - 1);
         const int64_t gi = co + (int64_t)zc * plane + col_off;
         if (FUSED) rv = r[gi];
-        pv = ld_once<R>(pin + gi);  // p_{k-1} is dead after this step
+        // p_{k-1} is dead after this step
+        if constexpr (NTH)
+            pv = ld_once<R>(pin + gi);
+        else
+            pv = pin[gi];
     };
 
     for (int k = tid; k < 2 * pitch * lrows; k += blockDim.x) {
@@ -670,7 +674,11 @@ __global__ __launch_bounds__(1024) void k_cocg_plane(
             const int64_t gz = co + (int64_t)min(z, nz - 1) * plane + col_off;
             if (FUSED) {
                 cplx_t<R>* dst = live ? pout + gz : my_sink;
-                st_once<R>(dst, xi);  // p_k: next read one whole step later
+                // p_k: next read one whole step later
+                if constexpr (NTH)
+                    st_once<R>(dst, xi);
+                else
+                    *dst = xi;
             }
             __syncthreads();
             const R dr = (R)(e_c - v_cur);
@@ -690,7 +698,11 @@ __global__ __launch_bounds__(1024) void k_cocg_plane(
             o.x = ax;
             o.y = ay;
             cplx_t<R>* ydst = live ? y + gz : my_sink;
-            st_once<R>(ydst, o);  // q: read once, by the update
+            // q: read once, by the update
+            if constexpr (NTH)
+                st_once<R>(ydst, o);
+            else
+                *ydst = o;
             if (FUSED) {
                 const double dx = (double)xi.x * ax - (double)xi.y * ay;
                 const double dy = (double)xi.x * ay + (double)xi.y * ax;
@@ -806,12 +818,26 @@ void fused_launch(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin, c
     Coef<R> cf;
     for (int m = 0; m < 7; ++m) cf.a[m] = (R)op->coef.a[m];
     dim3 grid(g.n_ytiles * g.n_z, w);
+    // The dead streams (p_{k-1} read; p_k and q written) take the
+    // non-temporal hint only when the block's vectors outgrow the last-level
+    // cache (256 MiB): with r, the p pair and q above 64 MiB each.  Below it
+    // q is still in the cache for the update kernel that reads it next, and
+    // the hint cost the junction batch 6 % (whole-plane) and 4 % (row-tiled);
+    // above it the hint gained 2 % on the 32x32x192 wire (201 MB per
+    // 64-column vector) and 3 % on the 64x64x256 one (537 MB per 32 columns).
+    const bool nth = (double)w * (double)op->N * sizeof(cplx_t<R>) > 64.0 * (1 << 20);
     if (g.whole_plane) {
-        if (g.lds > 65536) allow_large_lds((const void*)k_cocg_plane<RAD, R, FUSED>);
-        hipLaunchKernelGGL((k_cocg_plane<RAD, R, FUSED>), grid, dim3(g.nt), g.lds, s, r, pin, pout,
-                           y, reinterpret_cast<cplx_t<R>*>(op->d_sink), op->nx, op->ny, op->nz,
-                           g.zchunk, cf, op->coef.a[0], op->d_v, op->d_wz, shift, skip, kit, beta,
-                           part);
+        auto go_plane = [&](auto kern) {
+            if (g.lds > 65536) allow_large_lds((const void*)kern);
+            hipLaunchKernelGGL(kern, grid, dim3(g.nt), g.lds, s, r, pin, pout, y,
+                               reinterpret_cast<cplx_t<R>*>(op->d_sink), op->nx, op->ny, op->nz,
+                               g.zchunk, cf, op->coef.a[0], op->d_v, op->d_wz, shift, skip, kit,
+                               beta, part);
+        };
+        if (nth)
+            go_plane(k_cocg_plane<RAD, R, FUSED, true>);
+        else
+            go_plane(k_cocg_plane<RAD, R, FUSED, false>);
         return;
     }
     // y-tiles of a z-chunk grouped on one XCD; NEGF_ROWTILE_XCD=0 deals them
@@ -820,12 +846,9 @@ void fused_launch(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin, c
         const char* e = getenv("NEGF_ROWTILE_XCD");
         return (e && e[0] == '0') ? 0 : 1;
     }();
-    // p_k and q stored with the non-temporal hint only when one block of
-    // them outgrows the last-level cache: on the 64x64x256 wire (537 MB per
-    // 32-column vector) the hint gained 4 %, on the junction batch (at most
-    // 262 MB per 64-column vector) it cost 4 %, where q still comes from the
-    // cache for the update kernel that reads it next
-    const int nt_store = (double)w * (double)op->N * sizeof(cplx_t<R>) > 384.0 * (1 << 20);
+    // the row-tiled loads keep no hint: a neighbouring tile re-reads r and
+    // p_{k-1} rows as halo
+    const int nt_store = nth ? 1 : 0;
     auto go = [&](auto kern, int nt) {
         if (g.lds > 65536) allow_large_lds((const void*)kern);
         hipLaunchKernelGGL(kern, grid, dim3(nt), g.lds, s, r, pin, pout, y, op->nx, op->ny,
@@ -845,7 +868,10 @@ void prepare_fused(const negf_op* op) {
     // whole-plane kernel: the geometry does not depend on the z-chunking
     if (pts <= 1024) {
         const size_t lds = 2 * (size_t)(op->nx + 2 * RAD) * (op->ny + 2 * RAD) * sizeof(cplx_t<R>);
-        if (lds > 65536) allow_large_lds((const void*)k_cocg_plane<RAD, R, true>);
+        if (lds > 65536) {
+            allow_large_lds((const void*)k_cocg_plane<RAD, R, true, true>);
+            allow_large_lds((const void*)k_cocg_plane<RAD, R, true, false>);
+        }
     }
     // row-tiled kernel (also reachable for small planes through the tuner)
     for (int nt : {256, 1024}) {

@@ -13,7 +13,7 @@ sys.path.insert(0, str(ROOT))
 
 import bench  # noqa: E402
 
-KERNEL = "k_cocg_plane<6,double,true>"
+KERNEL = "k_cocg_plane<6,double,true,true>"
 
 
 def _fields():
@@ -40,7 +40,7 @@ def test_committed_counters_are_used_only_for_their_source():
 
 
 STAND_IN = """// stand-in source
-template <int RAD, typename R, bool FUSED>
+template <int RAD, typename R, bool FUSED, bool NTH>
 __global__ void k_cocg_plane(const R* r) {
     body();
 }
