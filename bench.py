@@ -358,14 +358,26 @@ def measure_rows(names):
             js = make_junctions(64)
             ops = [P.operator_from_wire(j) for j in js]
             es = [j.energies for j in js]
+            n_src = [len(rhs_columns(j)) for j in js]
             cols = 16
             run = lambda k: P.negf_transmission_batch(ops, es, tol=TOL, col_begin=0, col_count=k)
             run(1)
             (_, st), t = timed(lambda: run(cols))
             solves = sum(cols * e.size for e in es)
-            emit(row=name, workload=f"64 junctions 16^2x64..40^2x160, {cols} cols x all E",
+            emit(row=name, workload=f"64 junctions 16^2x64..40^2x160, first {cols} cols x all E",
                  form="batch, core B FP64", seconds=t, solves=solves, solves_per_s=solves / t,
                  statuses_ok=bool(np.all(st == 0)))
+            # the same count of columns per junction at a quarter and at three
+            # quarters of its absorbing region (8 + 8, one shard per call)
+            t_all, ok = 0.0, True
+            for f in (0.25, 0.75):
+                sh = [(int(f * n) - 4, 8) for n in n_src]
+                (_, st), t = timed(lambda: P.negf_transmission_batch(ops, es, tol=TOL, shards=sh))
+                t_all += t
+                ok = ok and bool(np.all(st == 0))
+            emit(row=name, workload=f"64 junctions 16^2x64..40^2x160, 8 cols at 1/4 and 8 at 3/4 "
+                 f"of each absorbing region x all E", form="batch (per-junction shards), core B FP64",
+                 seconds=t_all, solves=solves, solves_per_s=solves / t_all, statuses_ok=ok)
         elif name in ("full", "adjoint"):
             w = make_wire(4)
             op = P.operator_from_wire(w)

@@ -273,6 +273,19 @@ negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* ops, const ne
                                     const int32_t* n_e, const double* const* energies,
                                     double* const* T, int32_t* status, int32_t max_concurrent);
 
+/* negf_transmission_batch with a source-column shard per junction: junction
+ * i sums over its columns [col_begin[i], col_begin[i] + col_count[i]) (the
+ * meaning of negf_opts.col_begin / col_count, which these arrays replace;
+ * col_count 0 -> to the last column), e.g. to sample every junction at the
+ * same relative place in its absorbing region.  Equivalent to calling
+ * negf_transmission for each junction with its own shard; bit-identical.
+ *   col_begin, col_count   n_ops host values each, non-null, >= 0 */
+negf_status negf_transmission_batch_shards(int32_t n_ops, negf_op* const* ops,
+                                           const negf_opts* opts, const int32_t* n_e,
+                                           const double* const* energies, const int32_t* col_begin,
+                                           const int32_t* col_count, double* const* T,
+                                           int32_t* status, int32_t max_concurrent);
+
 /* Launch-shape autotuner for the multi-shift core (the batching form's
  * tuned block width, z-chunking and stencil kernel).  It times a short run of
  * probe_iters COCG iterations (0 -> one chunk: 128 iterations, 256 on grids of

@@ -31,6 +31,7 @@ EXPORTS = (
     "negf_solve_columns",
     "negf_transmission",
     "negf_transmission_batch",
+    "negf_transmission_batch_shards",
     "negf_tune",
     "negf_tune_cached",
     "negf_set_launch_shape",
@@ -118,6 +119,9 @@ def load(path: str | None = None):
     lib.negf_transmission_grad.argtypes = [vp, C.POINTER(negf_opts), C.c_int32, vp, vp, vp, vp]
     lib.negf_transmission_batch.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(negf_opts),
                                             vp, C.POINTER(vp), C.POINTER(vp), vp, C.c_int32]
+    lib.negf_transmission_batch_shards.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(negf_opts),
+                                                   vp, C.POINTER(vp), vp, vp, C.POINTER(vp), vp,
+                                                   C.c_int32]
     lib.negf_tune.argtypes = [vp, C.POINTER(negf_opts), C.c_int32, vp, C.c_int32,
                               C.POINTER(negf_tune_result)]
     lib.negf_tune_cached.argtypes = [vp, C.POINTER(negf_opts), C.c_int32, vp, C.c_int32,
@@ -135,7 +139,8 @@ def load(path: str | None = None):
     for name in ("negf_build_operator", "negf_apply_operator", "negf_apply_operator_noalloc",
                  "negf_solve_columns",
                  "negf_transmission", "negf_transmission_grad", "negf_transmission_batch",
-                 "negf_tune", "negf_set_launch_shape", "negf_current",
+                 "negf_transmission_batch_shards", "negf_tune", "negf_tune_cached",
+                 "negf_set_launch_shape", "negf_current",
                  "negf_spectral_transmission", "negf_eigenpairs"):
         getattr(lib, name).restype = C.c_int
     _lib = lib

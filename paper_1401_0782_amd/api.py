@@ -326,8 +326,11 @@ def negf_current(energies, T, bias, e_fermi: float, kT: float = 0.0, stream=None
     return out
 
 
-def negf_transmission_batch(ops, energies_list, max_concurrent=0, check=True, **opts):
-    """T(E) for many junctions at once; returns (list of T arrays, statuses)."""
+def negf_transmission_batch(ops, energies_list, max_concurrent=0, check=True, shards=None,
+                            **opts):
+    """T(E) for many junctions at once; returns (list of T arrays, statuses).
+    shards: optional per-junction (col_begin, col_count) pairs (each
+    junction's own source-column shard, negf_transmission_batch_shards)."""
     n = len(ops)
     es = [np.ascontiguousarray(e, dtype=np.float64) for e in energies_list]
     Ts = [np.zeros(e.size) for e in es]
@@ -338,8 +341,15 @@ def negf_transmission_batch(ops, energies_list, max_concurrent=0, check=True, **
     t_ptrs = (C.c_void_p * n)(*[t.ctypes.data for t in Ts])
     status = np.zeros(n, np.int32)
     o = _opts(**opts)
-    st = _lib().negf_transmission_batch(n, handles, C.byref(o), _ptr(n_e), e_ptrs, t_ptrs,
-                                        _ptr(status), int(max_concurrent))
+    if shards is not None:
+        sh = np.asarray(shards, np.int32).reshape(n, 2)
+        cb, cc = np.ascontiguousarray(sh[:, 0]), np.ascontiguousarray(sh[:, 1])
+        st = _lib().negf_transmission_batch_shards(n, handles, C.byref(o), _ptr(n_e), e_ptrs,
+                                                   _ptr(cb), _ptr(cc), t_ptrs, _ptr(status),
+                                                   int(max_concurrent))
+    else:
+        st = _lib().negf_transmission_batch(n, handles, C.byref(o), _ptr(n_e), e_ptrs, t_ptrs,
+                                            _ptr(status), int(max_concurrent))
     if check:
         _check(st)
     return Ts, status

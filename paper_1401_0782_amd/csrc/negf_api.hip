@@ -2493,10 +2493,11 @@ static negf_status batch_job_result(BatchJob* job, double* T) {
     return final_status(n_bad, n_break);
 }
 
-extern "C" negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* ops,
-                                               const negf_opts* opts, const int32_t* n_e,
-                                               const double* const* energies, double* const* T,
-                                               int32_t* status, int32_t max_concurrent) {
+// col_begin / col_count: per-op source-column shards (nullable: those of opts)
+static negf_status batch_impl(int32_t n_ops, negf_op* const* ops, const negf_opts* opts,
+                              const int32_t* n_e, const double* const* energies,
+                              const int32_t* col_begin, const int32_t* col_count,
+                              double* const* T, int32_t* status, int32_t max_concurrent) {
     g_last_error.clear();
     (void)hipGetLastError();
     if (n_ops < 1 || !ops || !n_e || !energies || !T) {
@@ -2518,13 +2519,27 @@ extern "C" negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* op
         set_error("the batch runs every junction on its operator's own stream; opts->stream must be NULL");
         return NEGF_E_INVALID_ARG;
     }
+    // each junction's options: the shared ones, with its own column shard
+    std::vector<negf_opts> per(n_ops);
+    for (int i = 0; i < n_ops; ++i) {
+        if (opts) per[i] = *opts;
+        else std::memset(&per[i], 0, sizeof(negf_opts));  // all defaults
+        if (col_begin) per[i].col_begin = col_begin[i];
+        if (col_count) per[i].col_count = col_count[i];
+        if (per[i].col_begin < 0 || per[i].col_count < 0) {
+            set_error("batch entry %d: negative column range", i);
+            return NEGF_E_INVALID_ARG;
+        }
+    }
     // largest first: work ~ points x source columns x energies
     std::vector<int> order(n_ops);
     std::vector<double> cost(n_ops);
     for (int i = 0; i < n_ops; ++i) {
         order[i] = i;
         const negf_op* op = ops[i];
-        cost[i] = (double)op->N * (double)(op->zr1 - op->zr0) * op->nx * op->ny * n_e[i];
+        const double cols = per[i].col_count > 0 ? (double)per[i].col_count
+                                                 : (double)(op->zr1 - op->zr0) * op->nx * op->ny;
+        cost[i] = (double)op->N * cols * n_e[i];
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     const int n_slots = std::max(1, std::min(n_ops, max_concurrent > 0 ? max_concurrent : 4));
@@ -2584,11 +2599,11 @@ extern "C" negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* op
             const int i = order[next++];
             negf_op* op = ops[i];
             Defaults d;
-            const negf_status s_opt = read_opts(opts, &d);
+            const negf_status s_opt = read_opts(&per[i], &d);
             take_buffers(k, op);
             if (s_opt != NEGF_OK || !batch_interleaves(d)) {
                 st[i] = (s_opt != NEGF_OK) ? s_opt
-                                           : transmission_impl(op, opts, n_e[i], energies[i], T[i], nullptr);
+                                           : transmission_impl(op, &per[i], n_e[i], energies[i], T[i], nullptr);
                 if (st[i] != NEGF_OK) msg[i] = g_last_error;
                 return_buffers(k, op);
                 continue;
@@ -2598,7 +2613,7 @@ extern "C" negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* op
             job->index = i;
             job->op = op;
             job->n_e = n_e[i];
-            const negf_status s_start = batch_job_start(job, opts, energies[i]);
+            const negf_status s_start = batch_job_start(job, &per[i], energies[i]);
             if (s_start != NEGF_OK) {
                 end_job(k, s_start);
                 continue;
@@ -2641,4 +2656,27 @@ extern "C" negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* op
         }
     }
     return first;
+}
+
+extern "C" negf_status negf_transmission_batch(int32_t n_ops, negf_op* const* ops,
+                                               const negf_opts* opts, const int32_t* n_e,
+                                               const double* const* energies, double* const* T,
+                                               int32_t* status, int32_t max_concurrent) {
+    return batch_impl(n_ops, ops, opts, n_e, energies, nullptr, nullptr, T, status,
+                      max_concurrent);
+}
+
+extern "C" negf_status negf_transmission_batch_shards(int32_t n_ops, negf_op* const* ops,
+                                                      const negf_opts* opts, const int32_t* n_e,
+                                                      const double* const* energies,
+                                                      const int32_t* col_begin,
+                                                      const int32_t* col_count, double* const* T,
+                                                      int32_t* status, int32_t max_concurrent) {
+    if (!col_begin || !col_count) {
+        g_last_error.clear();
+        set_error("null col_begin or col_count");
+        return NEGF_E_INVALID_ARG;
+    }
+    return batch_impl(n_ops, ops, opts, n_e, energies, col_begin, col_count, T, status,
+                      max_concurrent);
 }

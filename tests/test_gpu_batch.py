@@ -51,6 +51,47 @@ def test_batch_uneven_wire_junctions(gpu_lib):
         assert np.array_equal(T, P.negf_transmission(op, j.energies, **kw))
 
 
+def test_batch_shards_per_junction(gpu_lib):
+    """negf_transmission_batch_shards: each junction sums over its own column
+    shard (here 8 columns in the middle of its right absorbing region, and
+    its last 5 with col_count 0 meaning to the end); the per-junction T are
+    bit-identical to negf_transmission on the same shard, and for the small
+    junctions the shards of all columns add up to the oracle's T."""
+    import paper_1401_0782_amd as P
+    from workloads import rhs_columns
+
+    js = _junctions()
+    ops = [P.operator_from_wire(j) for j in js]
+    n_src = [len(rhs_columns(j)) for j in js]
+    es = [j.energies for j in js]
+    mid = [(n // 2 - 4, 8) for n in n_src]
+    Tm, st = P.negf_transmission_batch(ops, es, max_concurrent=3, tol=1e-12, shards=mid)
+    assert np.all(st == 0)
+    for j, op, T, (c0, cn) in zip(js, ops, Tm, mid):
+        assert np.array_equal(T, P.negf_transmission(op, j.energies, tol=1e-12, col_begin=c0,
+                                                     col_count=cn))
+    # three shards per junction: [0, c), [c, n - 5), [n - 5, end) add up to T
+    parts = []
+    for cut in ([(0, n // 3) for n in n_src], [(n // 3, n - 5 - n // 3) for n in n_src],
+                [(n - 5, 0) for n in n_src]):
+        T, st = P.negf_transmission_batch(ops, es, max_concurrent=3, tol=1e-12, shards=cut)
+        assert np.all(st == 0)
+        parts.append(T)
+    for k, j in enumerate(js[:3]):
+        total = parts[0][k] + parts[1][k] + parts[2][k]
+        assert np.max(np.abs(total - O.transmission(j, method="dense"))) <= 1e-8
+
+
+def test_batch_shards_reject_negative_ranges(gpu_lib):
+    import paper_1401_0782_amd as P
+    from paper_1401_0782_amd import NegfError
+
+    js = _junctions()[:2]
+    ops = [P.operator_from_wire(j) for j in js]
+    with pytest.raises(NegfError, match="negative column range"):
+        P.negf_transmission_batch(ops, [j.energies for j in js], shards=[(0, 4), (-1, 4)])
+
+
 def test_batch_unconverged_and_mixed_paths(gpu_lib):
     """A batch whose junctions all stop at max_iter reports NOT_CONVERGED per
     junction with the same T as single calls; mixed precision (the per-energy
