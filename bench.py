@@ -216,7 +216,8 @@ def cpu_baseline(seconds: float):
 
 # ---------------------------------------------------------- secondary rows
 FP64_PEAK_TFS = 78.6
-ROWS = ("small", "mixed", "batch", "full", "adjoint", "large", "spectral", "current", "copy")
+ROWS = ("small", "mixed", "batch", "full", "adjoint", "large", "spectral", "current", "copy",
+        "stream")
 
 
 def precision_forms(P, op, wire, n_cols=4, n_e=4):
@@ -401,6 +402,37 @@ def measure_rows(names):
                      "adjoint solves in the per-energy core", seconds=t,
                      item_solves_per_s=2 * cols * E.size / t,
                      projected_full_minutes=t * n / cols / 60.0)
+        elif name == "stream":
+            # the 32x32x192 workload the way a whole run takes it: source
+            # columns streamed through 64 slots (a slot refills at a chunk
+            # boundary as soon as its column has finished), here the first
+            # half of the 16,384 columns in 8 calls of 1024, one line each
+            w = make_wire(2)
+            op = P.operator_from_wire(w)
+            P.negf_set_launch_shape(op, 64, 192, 1)
+            E = w.energies
+            golden = json.loads(GOLDEN.read_text())["samples"] if GOLDEN.exists() else []
+            per, calls, t_all, worst = 1024, 8, 0.0, 0.0
+            for k in range(calls):
+                c0 = k * per
+                (T, d), t = timed(lambda: P.negf_transmission(op, E, n_cols=per, tol=TOL,
+                                                               col_begin=c0, col_count=per,
+                                                               block_width=64))
+                t_all += t
+                for smp in golden:
+                    if c0 <= smp["col"] < c0 + per:
+                        worst = max(worst, abs(float(d.t_col[smp["e_index"], smp["col"] - c0])
+                                               - smp["t_col"]))
+                emit(row=name, workload=f"wire 32x32x192 R=6 KB, columns {c0}..{c0 + per - 1} x "
+                     f"{E.size} E, streamed through 64 slots", form="core B FP64", seconds=t,
+                     solves_per_s=per * E.size / t, status=int(d.status),
+                     column_iterations=d.total_iters)
+            n_all = len(rhs_columns(w))
+            emit(row=name, workload=f"wire 32x32x192 R=6 KB, first {calls * per} of {n_all} "
+                 f"columns x {E.size} E", form="core B FP64, streamed", seconds=t_all,
+                 solves_per_s=calls * per * E.size / t_all,
+                 projected_full_minutes=t_all * n_all / (calls * per) / 60.0,
+                 max_abs_dt_vs_oracle_samples=worst)
         elif name == "large":
             w = make_wire(5)
             op = P.operator_from_wire(w)
