@@ -216,8 +216,8 @@ def cpu_baseline(seconds: float):
 
 # ---------------------------------------------------------- secondary rows
 FP64_PEAK_TFS = 78.6
-ROWS = ("small", "mixed", "batch", "full", "adjoint", "large", "spectral", "current", "copy",
-        "stream")
+ROWS = ("small", "mixed", "batch", "full", "adjoint", "large", "large_adjoint", "spectral",
+        "current", "copy", "stream")
 
 
 def precision_forms(P, op, wire, n_cols=4, n_e=4):
@@ -402,6 +402,31 @@ def measure_rows(names):
                      "adjoint solves in the per-energy core", seconds=t,
                      item_solves_per_s=2 * cols * E.size / t,
                      projected_full_minutes=t * n / cols / 60.0)
+        elif name == "large_adjoint":
+            # the 64x64x256 wire's gradient form: dT/dV summed over 16 selected
+            # energies (energies[::64]), on two 2-column shards (innermost and
+            # outermost absorbing plane)
+            w = make_wire(5)
+            op = P.operator_from_wire(w)
+            E = w.energies[::64]
+            n = len(rhs_columns(w))
+            wts = np.ones(E.size)
+            run = lambda c0, k: P.negf_transmission_grad(op, E, wts, tol=TOL, col_begin=c0,
+                                                         col_count=k, block_width=k)
+            run(n // 2, 1)
+            shards = [0, n - 2]
+            t_all = 0.0
+            for c0 in shards:  # one line per shard
+                _, t = timed(lambda: run(c0, 2))
+                t_all += t
+                emit(row=name, workload=f"wire 64x64x256 R=6 KB, cols {c0}..{c0 + 1} x {E.size} E",
+                     form="dT/dV shard", seconds=t, item_solves_per_s=2 * 2 * E.size / t)
+            cols = 2 * len(shards)
+            emit(row=name, workload=f"wire 64x64x256 R=6 KB, {cols} cols (shards at {shards}) "
+                 f"x {E.size} E", form="dT/dV: forward columns from the multi-shift core, "
+                 "adjoint solves in the per-energy core", seconds=t_all,
+                 item_solves_per_s=2 * cols * E.size / t_all,
+                 projected_full_hours=t_all * n / cols / 3600.0)
         elif name == "stream":
             # the 32x32x192 workload the way a whole run takes it: source
             # columns streamed through 64 slots (a slot refills at a chunk

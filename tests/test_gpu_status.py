@@ -128,6 +128,38 @@ def test_hostile_chain_restarts_recover_every_item(gpu_lib, hostile_chain):
     assert np.all(d.iters[failed] > d0.iters[failed])
 
 
+@pytest.mark.parametrize("max_iter", [3000, 20])
+def test_restarts_under_a_tight_iteration_cap(gpu_lib, hostile_chain, max_iter):
+    """A tight max_iter leaves items unconverged in the multi-shift core (and
+    at 20, with the per-energy core's 8 refinement passes of 20 iterations on
+    a 200-point chain, also in the COCG pass, so the QMR pass runs on what
+    COCG left): every item ends converged (and matches the oracle) or
+    flagged, the call reports the count of flagged items, and a restarted
+    item's iterations add up over its runs (more than the multi-shift run
+    alone)."""
+    import paper_1401_0782_amd as P
+    from paper_1401_0782_amd import _abi
+
+    w, cols, t_ref = hostile_chain
+    op = P.operator_from_wire(w)
+    kw = dict(n_cols=len(cols), check=False, tol=1e-12, max_iter=max_iter, optical=True,
+              core=P.NEGF_CORE_MULTISHIFT)
+    _, d0 = P.negf_transmission(op, w.energies, **kw)
+    _, d = P.negf_transmission(op, w.energies, recover=True, **kw)
+    failed0 = d0.item_status != _abi.NEGF_ITEM_CONVERGED
+    ok = d.item_status == _abi.NEGF_ITEM_CONVERGED
+    print(f"{int(failed0.sum())} failed in the multi-shift core, {int((~ok).sum())} after the "
+          f"restarts")
+    assert failed0.any()
+    assert np.all(np.abs(d.t_col[ok] - t_ref[ok]) <= 1e-8)
+    assert np.all(d.iters[failed0] > d0.iters[failed0])
+    if (~ok).any():
+        assert d.status == _abi.NEGF_E_NOT_CONVERGED or d.status == _abi.NEGF_E_BREAKDOWN
+        assert d.n_not_converged == int((~ok).sum())
+    else:
+        assert d.status == _abi.NEGF_OK
+
+
 def test_restart_needs_no_optical_request(gpu_lib, hostile_chain):
     """The restart mode runs the optical check itself: without the optical
     diagnostics requested, T is the same as with them."""
