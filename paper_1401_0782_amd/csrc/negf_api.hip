@@ -1299,8 +1299,9 @@ static negf_status run_per_energy_block(negf_op* op, const Defaults& d, int w, c
                     cplx_t<R>* pout = (it & 1) ? p : p2;
                     hipEvent_t e0, e1;
                     CHK(tm->next(&e0, &e1));
+                    // r, the p pair, q and the iterate d are touched every iteration
                     launch_cocg_apply<R>(op, r, pin, pout, q, w, shift, st.done, st.k, st.beta,
-                                         part_f, kbc, s, e0, e1);
+                                         part_f, kbc, s, e0, e1, true, 0, 5);
                     launch_reduce_alpha(part_f, nblk_f, st, s, op->kb.n_proj ? kbc : nullptr,
                                         op->kb.e, op->kb.n_proj);
                     // COCG: x += alpha p_k; QMR: the pending smoothed step from p_{k-1}

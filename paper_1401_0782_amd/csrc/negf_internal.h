@@ -189,12 +189,15 @@ void launch_reduce_alpha(const double2* part, int nblk, IterState st, hipStream_
                          int n_proj = 0);
 // fused p-update + operator apply + p^T q partials (stencil.hip); the projector
 // gather/scatter follow it.  ev0/ev1 (nullable) bracket the stencil kernel.
+// live_vectors: block vectors the caller's iteration touches (r, the p pair
+// and q in the multi-shift core; the iterate as well in the per-energy core),
+// which decides whether the dead streams take the non-temporal hint.
 template <typename R>
 void launch_cocg_apply(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin,
                        cplx_t<R>* pout, cplx_t<R>* q, int w, const double* shift, const int* skip,
                        const int* kit, const double2* beta, double2* part, double2* d_kbc,
                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, bool kb_scatter = true,
-                       int w_geom = 0);
+                       int w_geom = 0, int live_vectors = 4);
 // opts in the fused stencil kernels this op's grid can launch to more than
 // 64 KB of LDS (once per kernel and device; called when the op is built)
 void prepare_stencil_kernels(const negf_op* op);

@@ -813,19 +813,22 @@ void allow_large_lds(const void* kernel) {
 template <int RAD, typename R, bool FUSED>
 void fused_launch(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* pin, cplx_t<R>* pout,
                   cplx_t<R>* y, int w, int w_geom, const double* shift, const int* skip,
-                  const int* kit, const double2* beta, double2* part, hipStream_t s) {
+                  const int* kit, const double2* beta, double2* part, hipStream_t s,
+                  int live_vectors) {
     const FusedGeom g = fused_geom<RAD, R>(op, w_geom);
     Coef<R> cf;
     for (int m = 0; m < 7; ++m) cf.a[m] = (R)op->coef.a[m];
     dim3 grid(g.n_ytiles * g.n_z, w);
     // The dead streams (p_{k-1} read; p_k and q written) take the
-    // non-temporal hint only when the block's vectors outgrow the last-level
-    // cache (256 MiB): with r, the p pair and q above 64 MiB each.  Below it
-    // q is still in the cache for the update kernel that reads it next, and
-    // the hint cost the junction batch 6 % (whole-plane) and 4 % (row-tiled);
-    // above it the hint gained 2 % on the 32x32x192 wire (201 MB per
-    // 64-column vector) and 3 % on the 64x64x256 one (537 MB per 32 columns).
-    const bool nth = (double)w * (double)op->N * sizeof(cplx_t<R>) > 64.0 * (1 << 20);
+    // non-temporal hint only when the vectors the iteration touches outgrow
+    // the last-level cache (256 MiB).  Below it q is still in the cache for
+    // the kernel that reads it next: the hint cost the junction batch 6 %
+    // (whole-plane) and 4 % (row-tiled), and the multi-shift core 6 % on the
+    // 24x24x96 wire (4 x 57 MB), while the per-energy core there (5 x 57 MB)
+    // gained 5 % from it; above it the hint gained 2 % on the 32x32x192
+    // wire (4 x 201 MB) and 3 % on the 64x64x256 one (4 x 537 MB).
+    const bool nth = (double)live_vectors * (double)w * (double)op->N * sizeof(cplx_t<R>) >
+                     256.0 * (1 << 20);
     if (g.whole_plane) {
         auto go_plane = [&](auto kern) {
             if (g.lds > 65536) allow_large_lds((const void*)kern);
@@ -920,16 +923,17 @@ void launch_cocg_apply(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* p
                        cplx_t<R>* pout, cplx_t<R>* q, int w, const double* shift, const int* skip,
                        const int* kit, const double2* beta, double2* part, double2* d_kbc,
                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, bool kb_scatter,
-                       int w_geom) {
+                       int w_geom, int live_vectors) {
     if (ev0) (void)hipEventRecord(ev0, s);
     const int wg = w_geom > 0 ? w_geom : w;
+    const int lv = live_vectors;
     switch (op->R) {
-        case 1: fused_launch<1, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s); break;
-        case 2: fused_launch<2, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s); break;
-        case 3: fused_launch<3, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s); break;
-        case 4: fused_launch<4, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s); break;
-        case 5: fused_launch<5, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s); break;
-        default: fused_launch<6, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s); break;
+        case 1: fused_launch<1, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s, lv); break;
+        case 2: fused_launch<2, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s, lv); break;
+        case 3: fused_launch<3, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s, lv); break;
+        case 4: fused_launch<4, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s, lv); break;
+        case 5: fused_launch<5, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s, lv); break;
+        default: fused_launch<6, R, true>(op, r, pin, pout, q, w, wg, shift, skip, kit, beta, part, s, lv); break;
     }
     if (ev1) (void)hipEventRecord(ev1, s);
     if (op->kb.n_proj > 0) {
@@ -948,8 +952,8 @@ void launch_cocg_apply(const negf_op* op, const cplx_t<R>* r, const cplx_t<R>* p
 template void launch_cocg_apply<double>(const negf_op*, const double2*, const double2*, double2*,
                                         double2*, int, const double*, const int*, const int*,
                                         const double2*, double2*, double2*, hipStream_t,
-                                        hipEvent_t, hipEvent_t, bool, int);
+                                        hipEvent_t, hipEvent_t, bool, int, int);
 template void launch_cocg_apply<float>(const negf_op*, const float2*, const float2*, float2*,
                                        float2*, int, const double*, const int*, const int*,
                                        const double2*, double2*, double2*, hipStream_t,
-                                       hipEvent_t, hipEvent_t, bool, int);
+                                       hipEvent_t, hipEvent_t, bool, int, int);
