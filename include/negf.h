@@ -92,8 +92,12 @@ enum {
                                  max_iter or inaccurate are solved again, each
                                  as its own seed system, in the FP64
                                  per-energy core (COCG; items COCG still fails
-                                 then by QMR); their diagnostics are those of
-                                 the re-solve, iters the sum of both runs */
+                                 then by QMR); the optical-theorem check runs
+                                 whether or not negf_diag asks for it; the
+                                 re-solved items' diagnostics are those of the
+                                 re-solve, iters the sum over all runs.  In a
+                                 junction batch such junctions run one at a
+                                 time */
 };
 
 /* negf_opts.direction for negf_transmission */
