@@ -41,6 +41,8 @@ TIME_EVERY = 8
 LAUNCH_SHAPE = (192, 1)
 COUNTERS = ROOT / "profiles" / "stencil_wire32x32x192_counters.txt"
 GOLDEN = ROOT / "tests" / "golden" / "wire32x32x192_samples.json"
+# --rows stream: first source column and number of 1024-column calls
+STREAM_BEGIN, STREAM_CALLS = 0, 8
 KERNEL_SRC = ROOT / "paper_1401_0782_amd" / "csrc" / "stencil.hip"
 KERNEL_HELPERS = ROOT / "paper_1401_0782_amd" / "csrc" / "negf_internal.h"
 
@@ -430,16 +432,18 @@ def measure_rows(names):
         elif name == "stream":
             # the 32x32x192 workload the way a whole run takes it: source
             # columns streamed through 64 slots (a slot refills at a chunk
-            # boundary as soon as its column has finished), here the first
-            # half of the 16,384 columns in 8 calls of 1024, one line each
+            # boundary as soon as its column has finished), by default the
+            # first half of the 16,384 columns in 8 calls of 1024, one line
+            # each (--stream-begin / --stream-calls pick another range)
             w = make_wire(2)
             op = P.operator_from_wire(w)
             P.negf_set_launch_shape(op, 64, 192, 1)
             E = w.energies
             golden = json.loads(GOLDEN.read_text())["samples"] if GOLDEN.exists() else []
-            per, calls, t_all, worst = 1024, 8, 0.0, 0.0
+            per, calls, t_all, worst = 1024, STREAM_CALLS, 0.0, 0.0
+            first = STREAM_BEGIN
             for k in range(calls):
-                c0 = k * per
+                c0 = first + k * per
                 (T, d), t = timed(lambda: P.negf_transmission(op, E, n_cols=per, tol=TOL,
                                                                col_begin=c0, col_count=per,
                                                                block_width=64))
@@ -453,8 +457,8 @@ def measure_rows(names):
                      solves_per_s=per * E.size / t, status=int(d.status),
                      column_iterations=d.total_iters)
             n_all = len(rhs_columns(w))
-            emit(row=name, workload=f"wire 32x32x192 R=6 KB, first {calls * per} of {n_all} "
-                 f"columns x {E.size} E", form="core B FP64, streamed", seconds=t_all,
+            emit(row=name, workload=f"wire 32x32x192 R=6 KB, columns {first}..{first + calls * per - 1}"
+                 f" of {n_all} x {E.size} E", form="core B FP64, streamed", seconds=t_all,
                  solves_per_s=calls * per * E.size / t_all,
                  projected_full_minutes=t_all * n_all / (calls * per) / 60.0,
                  max_abs_dt_vs_oracle_samples=worst)
@@ -529,6 +533,10 @@ def main():
     ap.add_argument("--max-iter", type=int, default=60000)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stream-begin", type=int, default=0,
+                    help="--rows stream: first source column (a multiple of 1024)")
+    ap.add_argument("--stream-calls", type=int, default=8,
+                    help="--rows stream: calls of 1024 columns each")
     ap.add_argument("--no-precision-forms", action="store_true",
                     help="skip the mixed / FP64 comparison on a sample after the timed steps")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -564,6 +572,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.rows:
+        global STREAM_BEGIN, STREAM_CALLS
+        STREAM_BEGIN, STREAM_CALLS = args.stream_begin, args.stream_calls
         measure_rows(args.rows.split(","))
         return
     import paper_1401_0782_amd as P
