@@ -226,3 +226,44 @@ def test_enum_constants_match_header():
     assert len(found) >= 21
     for name, val in found.items():
         assert getattr(_abi, name) == val, name
+
+
+def test_header_is_plain_c_and_links_from_c(tmp_path):
+    """include/negf.h compiles as C99 and C++17 without warnings, and a plain
+    C program links against libnegf.so and calls an entry point that needs
+    no GPU (the version string) and one that rejects its arguments before any
+    device work."""
+    import shutil
+    import subprocess
+
+    from paper_1401_0782_amd import _abi
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    inc = ROOT / "include"
+    for lang, std in (("c", "-std=c99"), ("c++", "-std=c++17")):
+        r = subprocess.run([gcc if lang == "c" else (shutil.which("g++") or gcc), std, "-Wall",
+                            "-Wextra", "-Werror", "-fsyntax-only", "-x", lang,
+                            str(inc / "negf.h")], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
+    src = tmp_path / "use.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <string.h>\n#include "negf.h"\n'
+        "int main(void) {\n"
+        "    const char* v = negf_version();\n"
+        "    negf_op* op = 0;\n"
+        "    negf_status s = negf_build_operator(0, 2, 0, 0, 0, 0, &op);\n"
+        '    printf("%s|%d|%d\\n", v, (int)s, op == 0);\n'
+        "    return strlen(v) > 0 ? 0 : 1;\n}\n")
+    exe = tmp_path / "use"
+    lib = _abi.LIB_PATH
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", f"-I{inc}", str(src), "-o", str(exe),
+                        f"-L{lib.parent}", "-lnegf", f"-Wl,-rpath,{lib.parent}"],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    version, status, untouched = r.stdout.strip().split("|")
+    assert version.startswith("libnegf")
+    assert int(status) == _abi.NEGF_E_INVALID_ARG and untouched == "1"
